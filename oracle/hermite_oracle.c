@@ -1,0 +1,423 @@
+/*
+ * Plain FP64 CPU oracle for the Hermite method applied to the 3D scalar wave
+ * equation u_tt = c^2 (u_x1x1 + u_x2x2 + u_x3x3) on a periodic unit cube.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing on the product path links, loads or calls
+ * this file: only the test-suite, the smoke check and the benchmark's CPU
+ * baseline use it. It shares no code, header, table or constant generator
+ * with the HIP library.
+ *
+ * It is written to be read against Vargas, Chan, Hagstrom and Warburton,
+ * "GPU Acceleration of Hermite Methods for the Simulation of Wave Propagation"
+ * (arXiv:1609.09841):
+ *   - Sec. 2, Eq. 2: each node carries the scaled derivatives
+ *     h^{|i|}/i! D^i u for every multi-index i in [0,N]^3 (here N is called m).
+ *   - Sec. 2, Eq. 3: on each cell, the tensor-product polynomial of degree
+ *     2m+1 per variable in the cell variable xi = (x - x_centre)/h matches
+ *     the data of the 8 vertices; its coefficients are the centre data.
+ *   - Sec. 3.1, Alg. 1 and Alg. 2: that polynomial is built by applying the
+ *     1D Hermite matrix H along x1, then x2, then x3.
+ *   - Sec. 3.2, Alg. 3: derivative of the coefficient tensor by an index shift.
+ *   - Sec. 3.2, Alg. 4: the q-stage Horner loop of the Taylor evolution.
+ *   - Sec. 2 (after Eq. 5): the series is evaluated at the half step and the
+ *     process repeats on the other (dual/primal) grid.
+ *
+ * Readings of the paper used here (the paper states only the advection case):
+ *   - The wave equation is taken as the first-order system (u, u_t). Inside
+ *     the method u_t is carried as vt = (h/c) u_t, so that in the cell
+ *     variable xi and the half-step time sigma = (t - t_n)/tau the system is
+ *     u_sigma = lam * vt, vt_sigma = lam * Lap_xi u with lam = c*tau/h.
+ *   - The time step in Alg. 4 is the half step tau = dt/2.
+ *   - The derivative matrix has indices 0..2m+1.
+ *   - Dual node (i+1/2, j+1/2, k+1/2)h is stored at index (i, j, k); the dual
+ *     cell with lower corner (i, j, k) writes primal node (i+1, j+1, k+1).
+ *   - "Multi-stage" evolution is classical 4-stage Runge-Kutta on the cell
+ *     ODE dW/dsigma = L W, with S substeps per half step.
+ *
+ * Array layout of a grid field: [d3][d2][d1][k][j][i], i (x1) fastest, the
+ * tensor u[m3][m2][m1][n3][n2][n1] of Sec. 3.1. A two-field state is
+ * [f][d3][d2][d1][k][j][i] with f = 0 for u and f = 1 for u_t.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXM 4
+#define OR_MAXP (2 * OR_MAXM + 2)
+
+/* binomial coefficient, small arguments */
+static long double or_binom(int a, int b)
+{
+    if (b < 0 || b > a) return 0.0L;
+    long double r = 1.0L;
+    for (int i = 1; i <= b; ++i) r = r * (long double)(a - b + i) / (long double)i;
+    return r;
+}
+
+/*
+ * The 1D Hermite matrix H (Sec. 3.1; its construction is deferred by the
+ * paper to its reference on Hermite method variations). With P = 2m+2,
+ * H is the inverse of the confluent Vandermonde matrix V whose row
+ * (side, k) holds the k-th Taylor coefficient, at xi = -1/2 (side 0) or
+ * xi = +1/2 (side 1), of the monomial xi^j:  V[(side,k)][j] = C(j,k) xi^(j-k).
+ * So b = H * data maps the scaled derivatives [L0..Lm, R0..Rm] of the two
+ * end nodes to the monomial coefficients b_0..b_{2m+1} about the centre.
+ * Gauss-Jordan elimination with partial pivoting in long double, rounded to
+ * double at the end. H is row-major, H[j*P + r], r = side*(m+1) + k.
+ * Returns 0, or -1 for m outside [1, 4].
+ */
+int oracle_hermite_matrix(int m, double *H)
+{
+    if (m < 1 || m > OR_MAXM) return -1;
+    const int M = m + 1, P = 2 * m + 2;
+    long double A[OR_MAXP][2 * OR_MAXP];
+    for (int side = 0; side < 2; ++side) {
+        const long double x = side ? 0.5L : -0.5L;
+        for (int k = 0; k < M; ++k) {
+            const int r = side * M + k;
+            for (int j = 0; j < P; ++j) {
+                long double v = 0.0L;
+                if (j >= k) v = or_binom(j, k) * powl(x, (long double)(j - k));
+                A[r][j] = v;
+            }
+            for (int j = 0; j < P; ++j) A[r][P + j] = (r == j) ? 1.0L : 0.0L;
+        }
+    }
+    for (int col = 0; col < P; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < P; ++r)
+            if (fabsl(A[r][col]) > fabsl(A[piv][col])) piv = r;
+        if (A[piv][col] == 0.0L) return -2;
+        if (piv != col)
+            for (int j = 0; j < 2 * P; ++j) {
+                long double t = A[col][j];
+                A[col][j] = A[piv][j];
+                A[piv][j] = t;
+            }
+        const long double d = A[col][col];
+        for (int j = 0; j < 2 * P; ++j) A[col][j] /= d;
+        for (int r = 0; r < P; ++r) {
+            if (r == col || A[r][col] == 0.0L) continue;
+            const long double f = A[r][col];
+            for (int j = 0; j < 2 * P; ++j) A[r][j] -= f * A[col][j];
+        }
+    }
+    /* A's right half is V^{-1}: rows are coefficient indices j, columns data r */
+    for (int j = 0; j < P; ++j)
+        for (int r = 0; r < P; ++r) H[j * P + r] = (double)A[j][P + r];
+    return 0;
+}
+
+/*
+ * Alg. 1 generalised to any axis: apply the P x P matrix H along one axis of
+ * a P^3 tensor T[a3][a2][a1] (a1 fastest). axis 0 is x1, 1 is x2, 2 is x3.
+ */
+static void or_apply_axis(int P, const double *H, int axis, const double *in, double *out)
+{
+    for (int a3 = 0; a3 < P; ++a3)
+        for (int a2 = 0; a2 < P; ++a2)
+            for (int a1 = 0; a1 < P; ++a1) {
+                int t = (axis == 0) ? a1 : (axis == 1) ? a2 : a3;
+                double c = 0.0;
+                for (int k = 0; k < P; ++k) {
+                    int b1 = a1, b2 = a2, b3 = a3;
+                    if (axis == 0) b1 = k;
+                    else if (axis == 1) b2 = k;
+                    else b3 = k;
+                    c += H[t * P + k] * in[(b3 * P + b2) * P + b1];
+                }
+                out[(a3 * P + a2) * P + a1] = c;
+            }
+}
+
+/*
+ * Alg. 2: polynomial reconstruction of one cell. uloc is the local rank-3
+ * tensor of the 8 vertices, uloc[a3][a2][a1] with a = side*(m+1) + derivative
+ * order per axis; R receives the monomial coefficients R[j3][j2][j1] of the
+ * interpolant in xi (Eq. 3).
+ */
+void oracle_interpolate_cell(int m, const double *H, const double *uloc, double *R)
+{
+    const int P = 2 * m + 2;
+    double t1[OR_MAXP * OR_MAXP * OR_MAXP], t2[OR_MAXP * OR_MAXP * OR_MAXP];
+    or_apply_axis(P, H, 0, uloc, t1);
+    or_apply_axis(P, H, 1, t1, t2);
+    or_apply_axis(P, H, 2, t2, R);
+}
+
+/*
+ * Alg. 3 in the cell variable xi (h = 1 there): differentiate the coefficient
+ * tensor along one axis, (D W)[j] = (j+1) W[j+1], zero at the top index.
+ */
+static void or_diff_axis(int P, int axis, const double *W, double *out)
+{
+    for (int j3 = 0; j3 < P; ++j3)
+        for (int j2 = 0; j2 < P; ++j2)
+            for (int j1 = 0; j1 < P; ++j1) {
+                int t = (axis == 0) ? j1 : (axis == 1) ? j2 : j3;
+                double v = 0.0;
+                if (t < P - 1) {
+                    int b1 = j1, b2 = j2, b3 = j3;
+                    if (axis == 0) b1 = t + 1;
+                    else if (axis == 1) b2 = t + 1;
+                    else b3 = t + 1;
+                    v = (double)(t + 1) * W[(b3 * P + b2) * P + b1];
+                }
+                out[(j3 * P + j2) * P + j1] = v;
+            }
+}
+
+/* Laplacian in xi: sum over axes of Alg. 3 applied twice. */
+void oracle_laplacian(int m, const double *W, double *out)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    double d1[OR_MAXP * OR_MAXP * OR_MAXP], d2[OR_MAXP * OR_MAXP * OR_MAXP];
+    for (int t = 0; t < n3; ++t) out[t] = 0.0;
+    for (int axis = 0; axis < 3; ++axis) {
+        or_diff_axis(P, axis, W, d1);
+        or_diff_axis(P, axis, d1, d2);
+        for (int t = 0; t < n3; ++t) out[t] += d2[t];
+    }
+}
+
+/* The cell operator of the first-order system: L(a, b) = lam * (b, Lap a). */
+static void or_apply_L(int m, double lam, const double *a, const double *b, double *la, double *lb)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    oracle_laplacian(m, a, lb);
+    for (int t = 0; t < n3; ++t) {
+        la[t] = lam * b[t];
+        lb[t] = lam * lb[t];
+    }
+}
+
+/*
+ * Alg. 4 for the wave system: Horner loop over k = q..1 of
+ *   W <- R + (1/k) L W,
+ * i.e. (Wu, Wv) <- (Ru + (lam/k) Wv, Rv + (lam/k) Lap Wu), both from the old W.
+ * Ru, Rv are overwritten with the evolved coefficients at sigma = 1.
+ */
+void oracle_evolve_taylor(int m, int q, double lam, double *Ru, double *Rv)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    double wu[OR_MAXP * OR_MAXP * OR_MAXP], wv[OR_MAXP * OR_MAXP * OR_MAXP];
+    double lu[OR_MAXP * OR_MAXP * OR_MAXP], lv[OR_MAXP * OR_MAXP * OR_MAXP];
+    memcpy(wu, Ru, sizeof(double) * n3);
+    memcpy(wv, Rv, sizeof(double) * n3);
+    for (int k = q; k >= 1; --k) {
+        or_apply_L(m, lam, wu, wv, lu, lv);
+        for (int t = 0; t < n3; ++t) {
+            wu[t] = Ru[t] + lu[t] / (double)k;
+            wv[t] = Rv[t] + lv[t] / (double)k;
+        }
+    }
+    memcpy(Ru, wu, sizeof(double) * n3);
+    memcpy(Rv, wv, sizeof(double) * n3);
+}
+
+/*
+ * Classical 4-stage Runge-Kutta on dW/dsigma = L W over sigma in [0, 1] with
+ * S equal substeps (the abstract's multi-stage local evolution).
+ */
+void oracle_evolve_rk4(int m, int S, double lam, double *Ru, double *Rv)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    const double dl = 1.0 / (double)S;
+    double k1u[OR_MAXP * OR_MAXP * OR_MAXP], k1v[OR_MAXP * OR_MAXP * OR_MAXP];
+    double k2u[OR_MAXP * OR_MAXP * OR_MAXP], k2v[OR_MAXP * OR_MAXP * OR_MAXP];
+    double k3u[OR_MAXP * OR_MAXP * OR_MAXP], k3v[OR_MAXP * OR_MAXP * OR_MAXP];
+    double k4u[OR_MAXP * OR_MAXP * OR_MAXP], k4v[OR_MAXP * OR_MAXP * OR_MAXP];
+    double yu[OR_MAXP * OR_MAXP * OR_MAXP], yv[OR_MAXP * OR_MAXP * OR_MAXP];
+    for (int s = 0; s < S; ++s) {
+        or_apply_L(m, lam, Ru, Rv, k1u, k1v);
+        for (int t = 0; t < n3; ++t) { yu[t] = Ru[t] + 0.5 * dl * k1u[t]; yv[t] = Rv[t] + 0.5 * dl * k1v[t]; }
+        or_apply_L(m, lam, yu, yv, k2u, k2v);
+        for (int t = 0; t < n3; ++t) { yu[t] = Ru[t] + 0.5 * dl * k2u[t]; yv[t] = Rv[t] + 0.5 * dl * k2v[t]; }
+        or_apply_L(m, lam, yu, yv, k3u, k3v);
+        for (int t = 0; t < n3; ++t) { yu[t] = Ru[t] + dl * k3u[t]; yv[t] = Rv[t] + dl * k3v[t]; }
+        or_apply_L(m, lam, yu, yv, k4u, k4v);
+        for (int t = 0; t < n3; ++t) {
+            Ru[t] += dl / 6.0 * (k1u[t] + 2.0 * k2u[t] + 2.0 * k3u[t] + k4u[t]);
+            Rv[t] += dl / 6.0 * (k1v[t] + 2.0 * k2v[t] + 2.0 * k3v[t] + k4v[t]);
+        }
+    }
+}
+
+/*
+ * Gather the local tensor of the cell whose lower corner is node (i, j, k) of
+ * a periodic grid field g[d3][d2][d1][k][j][i] (Sec. 3.1: the (m+1)^3 values
+ * of each of the 8 vertices). uloc[a3][a2][a1], a = side*(m+1) + d.
+ */
+void oracle_gather_cell(int n, int m, const double *g, int i, int j, int k, double *uloc)
+{
+    const int M = m + 1, P = 2 * M;
+    const long nn = (long)n * n * n;
+    for (int s3 = 0; s3 < 2; ++s3)
+        for (int s2 = 0; s2 < 2; ++s2)
+            for (int s1 = 0; s1 < 2; ++s1) {
+                const long node = ((long)((k + s3) % n) * n + (j + s2) % n) * n + (i + s1) % n;
+                for (int d3 = 0; d3 < M; ++d3)
+                    for (int d2 = 0; d2 < M; ++d2)
+                        for (int d1 = 0; d1 < M; ++d1) {
+                            const long src = (long)((d3 * M + d2) * M + d1) * nn + node;
+                            const int a1 = s1 * M + d1, a2 = s2 * M + d2, a3 = s3 * M + d3;
+                            uloc[(a3 * P + a2) * P + a1] = g[src];
+                        }
+            }
+}
+
+/* evo: 0 = Taylor (param = q), 1 = RK4 (param = substeps S) */
+static void or_evolve(int m, int evo, int param, double lam, double *Ru, double *Rv)
+{
+    if (evo == 0) oracle_evolve_taylor(m, param, lam, Ru, Rv);
+    else oracle_evolve_rk4(m, param, lam, Ru, Rv);
+}
+
+/*
+ * One half step on a periodic grid (Sec. 2): for every cell of the source grid
+ * interpolate (Alg. 2), evolve through the half step (Alg. 4 or RK4) and keep
+ * the coefficients with every index <= m as the data of the node at the cell
+ * centre on the other grid. src and dst hold two fields, [f][M^3][n^3], in the
+ * internal variables (u, vt). to_dual = 1: primal -> dual, the cell with lower
+ * corner (i,j,k) writes dual (i,j,k); to_dual = 0: dual -> primal, writes
+ * primal (i+1, j+1, k+1) mod n.
+ */
+void oracle_half_step(int n, int m, const double *H, double lam, int evo, int param,
+                      const double *src, double *dst, int to_dual)
+{
+    const int M = m + 1, P = 2 * M, M3 = M * M * M;
+    const long nn = (long)n * n * n;
+    const int off = to_dual ? 0 : 1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j) {
+            double uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
+            double Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
+            for (int i = 0; i < n; ++i) {
+                oracle_gather_cell(n, m, src, i, j, k, uloc);
+                oracle_gather_cell(n, m, src + (long)M3 * nn, i, j, k, vloc);
+                oracle_interpolate_cell(m, H, uloc, Ru);
+                oracle_interpolate_cell(m, H, vloc, Rv);
+                or_evolve(m, evo, param, lam, Ru, Rv);
+                const long node = ((long)((k + off) % n) * n + (j + off) % n) * n + (i + off) % n;
+                for (int d3 = 0; d3 < M; ++d3)
+                    for (int d2 = 0; d2 < M; ++d2)
+                        for (int d1 = 0; d1 < M; ++d1) {
+                            const int dd = (d3 * M + d2) * M + d1;
+                            const int jj = (d3 * P + d2) * P + d1;
+                            dst[(long)dd * nn + node] = Ru[jj];
+                            dst[(long)(M3 + dd) * nn + node] = Rv[jj];
+                        }
+            }
+        }
+}
+
+/*
+ * Full run: u and ut (scaled derivatives of u and u_t on the primal grid,
+ * each [M^3][n^3]) are advanced by nsteps full steps in place. dt = cfl*h/c,
+ * tau = dt/2, lam = c*tau/h. Returns 0, or a negative value on bad input.
+ */
+int oracle_run(int n, int m, double cfl, double c, int evo, int param, int nsteps,
+               double *u, double *ut)
+{
+    if (n < 1 || m < 1 || m > OR_MAXM || !(cfl > 0.0) || !(c > 0.0) || nsteps < 0 || param < 1)
+        return -1;
+    const int M = m + 1, P = 2 * M, M3 = M * M * M;
+    const long nn = (long)n * n * n, sz = (long)M3 * nn;
+    const double h = 1.0 / (double)n;
+    const double dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    double H[OR_MAXP * OR_MAXP];
+    if (oracle_hermite_matrix(m, H) != 0) return -2;
+    (void)P;
+    double *a = (double *)malloc(sizeof(double) * 2 * sz);
+    double *b = (double *)malloc(sizeof(double) * 2 * sz);
+    if (!a || !b) { free(a); free(b); return -3; }
+    for (long t = 0; t < sz; ++t) { a[t] = u[t]; a[sz + t] = (h / c) * ut[t]; }
+    for (int s = 0; s < nsteps; ++s) {
+        oracle_half_step(n, m, H, lam, evo, param, a, b, 1);
+        oracle_half_step(n, m, H, lam, evo, param, b, a, 0);
+    }
+    for (long t = 0; t < sz; ++t) { u[t] = a[t]; ut[t] = (c / h) * a[sz + t]; }
+    free(a);
+    free(b);
+    return 0;
+}
+
+/*
+ * Local (non-periodic) dependency cone of one primal node after nsteps full
+ * steps, for sampled checks of large grids: the node (i0, j0, k0) after
+ * nsteps full steps depends only on the (2*nsteps+1)^3 primal nodes around
+ * it. Runs the same cell algorithm on that box (with periodic wrap of the
+ * source indices) and returns the node's 2*M^3 values, u then u_t.
+ */
+int oracle_point(int n, int m, double cfl, double c, int evo, int param, int nsteps,
+                 const double *u, const double *ut, int i0, int j0, int k0, double *out)
+{
+    if (n < 1 || m < 1 || m > OR_MAXM || nsteps < 1 || param < 1) return -1;
+    const int M = m + 1, P = 2 * M, M3 = M * M * M;
+    const long nn = (long)n * n * n;
+    const double h = 1.0 / (double)n;
+    const double dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    double H[OR_MAXP * OR_MAXP];
+    if (oracle_hermite_matrix(m, H) != 0) return -2;
+    /* box of primal nodes i0-s .. i0+s; box side w shrinks by one per half step */
+    int w = 2 * nsteps + 1;
+    double *box = (double *)malloc(sizeof(double) * 2 * M3 * (long)w * w * w);
+    if (!box) return -3;
+    for (int f = 0; f < 2; ++f)
+        for (int dd = 0; dd < M3; ++dd)
+            for (int z = 0; z < w; ++z)
+                for (int y = 0; y < w; ++y)
+                    for (int x = 0; x < w; ++x) {
+                        int gi = ((i0 - nsteps + x) % n + n) % n;
+                        int gj = ((j0 - nsteps + y) % n + n) % n;
+                        int gk = ((k0 - nsteps + z) % n + n) % n;
+                        double v = (f == 0 ? u : ut)[(long)dd * nn + ((long)gk * n + gj) * n + gi];
+                        if (f == 1) v *= h / c;
+                        box[(((long)(f * M3 + dd) * w + z) * w + y) * w + x] = v;
+                    }
+    for (int hs = 0; hs < 2 * nsteps; ++hs) {
+        const int wn = w - 1;
+        double *nb = (double *)malloc(sizeof(double) * 2 * M3 * (long)wn * wn * wn);
+        if (!nb) { free(box); return -3; }
+        for (int z = 0; z < wn; ++z)
+            for (int y = 0; y < wn; ++y)
+                for (int x = 0; x < wn; ++x) {
+                    double uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
+                    for (int f = 0; f < 2; ++f) {
+                        double *loc = f ? vloc : uloc;
+                        for (int s3 = 0; s3 < 2; ++s3)
+                            for (int s2 = 0; s2 < 2; ++s2)
+                                for (int s1 = 0; s1 < 2; ++s1)
+                                    for (int d3 = 0; d3 < M; ++d3)
+                                        for (int d2 = 0; d2 < M; ++d2)
+                                            for (int d1 = 0; d1 < M; ++d1) {
+                                                int dd = (d3 * M + d2) * M + d1;
+                                                long sidx = (((long)(f * M3 + dd) * w + z + s3) * w + y + s2) * w + x + s1;
+                                                loc[((s3 * M + d3) * P + s2 * M + d2) * P + s1 * M + d1] = box[sidx];
+                                            }
+                    }
+                    double Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
+                    oracle_interpolate_cell(m, H, uloc, Ru);
+                    oracle_interpolate_cell(m, H, vloc, Rv);
+                    or_evolve(m, evo, param, lam, Ru, Rv);
+                    for (int d3 = 0; d3 < M; ++d3)
+                        for (int d2 = 0; d2 < M; ++d2)
+                            for (int d1 = 0; d1 < M; ++d1) {
+                                int dd = (d3 * M + d2) * M + d1, jj = (d3 * P + d2) * P + d1;
+                                nb[(((long)dd * wn + z) * wn + y) * wn + x] = Ru[jj];
+                                nb[(((long)(M3 + dd) * wn + z) * wn + y) * wn + x] = Rv[jj];
+                            }
+                }
+        free(box);
+        box = nb;
+        w = wn;
+    }
+    /* w == 1: the remaining node is primal (i0, j0, k0) */
+    for (int dd = 0; dd < M3; ++dd) {
+        out[dd] = box[dd];
+        out[M3 + dd] = (c / h) * box[M3 + dd];
+    }
+    free(box);
+    return 0;
+}

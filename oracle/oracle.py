@@ -1,0 +1,224 @@
+"""Python side of the CPU oracle (test infrastructure only).
+
+Only ``tests/``, the smoke check and the benchmark's ``cpu_baseline`` leg may
+import this module. It loads ``liboracle.so`` built from ``hermite_oracle.c``
+with gcc, and adds an exact-rational construction of the 1D Hermite matrix.
+
+Citations refer to Vargas, Chan, Hagstrom, Warburton, "GPU Acceleration of
+Hermite Methods for the Simulation of Wave Propagation" (arXiv:1609.09841).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hermite_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+__all__ = [
+    "build_oracle", "load", "exact_hermite_matrix", "hermite_matrix",
+    "interpolate_cell", "laplacian", "evolve_taylor", "evolve_rk4",
+    "gather_cell", "half_step", "run", "point", "exact_q",
+]
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build_oracle(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i, d = ctypes.c_int, ctypes.c_double
+    lib.oracle_hermite_matrix.argtypes = [i, dp]
+    lib.oracle_hermite_matrix.restype = i
+    lib.oracle_interpolate_cell.argtypes = [i, dp, dp, dp]
+    lib.oracle_interpolate_cell.restype = None
+    lib.oracle_laplacian.argtypes = [i, dp, dp]
+    lib.oracle_laplacian.restype = None
+    lib.oracle_evolve_taylor.argtypes = [i, i, d, dp, dp]
+    lib.oracle_evolve_taylor.restype = None
+    lib.oracle_evolve_rk4.argtypes = [i, i, d, dp, dp]
+    lib.oracle_evolve_rk4.restype = None
+    lib.oracle_gather_cell.argtypes = [i, i, dp, i, i, i, dp]
+    lib.oracle_gather_cell.restype = None
+    lib.oracle_half_step.argtypes = [i, i, dp, d, i, i, dp, dp, i]
+    lib.oracle_half_step.restype = None
+    lib.oracle_run.argtypes = [i, i, d, d, i, i, i, dp, dp]
+    lib.oracle_run.restype = i
+    lib.oracle_point.argtypes = [i, i, d, d, i, i, i, dp, dp, i, i, i, dp]
+    lib.oracle_point.restype = i
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def exact_q(m: int) -> int:
+    """Stage count at which the Taylor series of the wave system is exact on
+    the cell space: each axis absorbs at most m second derivatives of a
+    degree-(2m+1) polynomial, so Lap^(3m+1) = 0 and L^(6m+2) = 0."""
+    return 6 * m + 1
+
+
+def exact_hermite_matrix(m: int) -> list[list[Fraction]]:
+    """Brute-force exact solve of the 1D two-point Hermite interpolation system.
+
+    Unknowns: monomial coefficients b_0..b_{2m+1} of p(xi) about the cell
+    centre. Equations: the k-th Taylor coefficient of p at xi = -1/2 and at
+    xi = +1/2 equals the given scaled derivative (Sec. 2, Eq. 2-3). Solved by
+    Gauss-Jordan elimination over the rationals; returns H with b = H @ data,
+    data ordered [L0..Lm, R0..Rm].
+    """
+    M, P = m + 1, 2 * m + 2
+    half = Fraction(1, 2)
+    rows = []
+    for side in (0, 1):
+        x = -half if side == 0 else half
+        for k in range(M):
+            row = []
+            for j in range(P):
+                if j < k:
+                    row.append(Fraction(0))
+                else:
+                    # k-th Taylor coefficient of xi^j at x: C(j,k) x^(j-k)
+                    c = Fraction(1)
+                    for t in range(1, k + 1):
+                        c = c * (j - k + t) / t
+                    row.append(c * x ** (j - k))
+            rows.append(row)
+    aug = [rows[r] + [Fraction(int(r == c)) for c in range(P)] for r in range(P)]
+    for col in range(P):
+        piv = next(r for r in range(col, P) if aug[r][col] != 0)
+        aug[col], aug[piv] = aug[piv], aug[col]
+        d = aug[col][col]
+        aug[col] = [v / d for v in aug[col]]
+        for r in range(P):
+            if r != col and aug[r][col] != 0:
+                f = aug[r][col]
+                aug[r] = [a - f * b for a, b in zip(aug[r], aug[col])]
+    return [[aug[j][P + r] for r in range(P)] for j in range(P)]
+
+
+def hermite_matrix(m: int) -> np.ndarray:
+    """The C oracle's H (long-double Gauss-Jordan rounded to FP64)."""
+    P = 2 * m + 2
+    H = np.zeros((P, P))
+    rc = load().oracle_hermite_matrix(m, _ptr(H))
+    if rc != 0:
+        raise ValueError(f"oracle_hermite_matrix({m}) failed: {rc}")
+    return H
+
+
+def interpolate_cell(m: int, uloc: np.ndarray, H: np.ndarray | None = None) -> np.ndarray:
+    """Alg. 2 on one cell: uloc[a3][a2][a1] -> monomial coefficients R[j3][j2][j1]."""
+    P = 2 * m + 2
+    H = hermite_matrix(m) if H is None else np.ascontiguousarray(H, dtype=np.float64)
+    uloc = np.ascontiguousarray(uloc, dtype=np.float64).reshape(P, P, P)
+    R = np.zeros((P, P, P))
+    load().oracle_interpolate_cell(m, _ptr(H), _ptr(uloc), _ptr(R))
+    return R
+
+
+def laplacian(m: int, W: np.ndarray) -> np.ndarray:
+    P = 2 * m + 2
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(P, P, P)
+    out = np.zeros((P, P, P))
+    load().oracle_laplacian(m, _ptr(W), _ptr(out))
+    return out
+
+
+def evolve_taylor(m: int, q: int, lam: float, Ru: np.ndarray, Rv: np.ndarray):
+    P = 2 * m + 2
+    a = np.array(Ru, dtype=np.float64).reshape(P, P, P).copy()
+    b = np.array(Rv, dtype=np.float64).reshape(P, P, P).copy()
+    load().oracle_evolve_taylor(m, q, lam, _ptr(a), _ptr(b))
+    return a, b
+
+
+def evolve_rk4(m: int, S: int, lam: float, Ru: np.ndarray, Rv: np.ndarray):
+    P = 2 * m + 2
+    a = np.array(Ru, dtype=np.float64).reshape(P, P, P).copy()
+    b = np.array(Rv, dtype=np.float64).reshape(P, P, P).copy()
+    load().oracle_evolve_rk4(m, S, lam, _ptr(a), _ptr(b))
+    return a, b
+
+
+def gather_cell(n: int, m: int, g: np.ndarray, i: int, j: int, k: int) -> np.ndarray:
+    P = 2 * m + 2
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.zeros((P, P, P))
+    load().oracle_gather_cell(n, m, _ptr(g), i, j, k, _ptr(out))
+    return out
+
+
+def half_step(n: int, m: int, lam: float, src: np.ndarray, to_dual: bool,
+              evolution: str = "taylor", param: int | None = None) -> np.ndarray:
+    """One half step on internal variables (u, (h/c) u_t), arrays [2][M^3][n^3]."""
+    evo, param = _evo(m, evolution, param)
+    H = hermite_matrix(m)
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    dst = np.zeros_like(src)
+    load().oracle_half_step(n, m, _ptr(H), lam, evo, param, _ptr(src), _ptr(dst), int(bool(to_dual)))
+    return dst
+
+
+def _evo(m, evolution, param):
+    if evolution == "taylor":
+        return 0, exact_q(m) if param is None else int(param)
+    if evolution == "rk4":
+        return 1, 1 if param is None else int(param)
+    raise ValueError(evolution)
+
+
+def run(n: int, m: int, cfl: float, c: float, u: np.ndarray, ut: np.ndarray, nsteps: int,
+        evolution: str = "taylor", param: int | None = None):
+    """Advance primal-grid scaled derivatives (u, u_t), each [M^3][n^3] (any
+    shape with that many elements, layout [d3][d2][d1][k][j][i]), by nsteps
+    full steps. Returns new (u, ut) arrays of the same shape."""
+    evo, param = _evo(m, evolution, param)
+    shape = np.shape(u)
+    a = np.array(u, dtype=np.float64).ravel().copy()
+    b = np.array(ut, dtype=np.float64).ravel().copy()
+    M3 = (m + 1) ** 3
+    assert a.size == M3 * n ** 3 and b.size == a.size
+    rc = load().oracle_run(n, m, float(cfl), float(c), evo, param, int(nsteps), _ptr(a), _ptr(b))
+    if rc != 0:
+        raise ValueError(f"oracle_run failed: {rc}")
+    return a.reshape(shape), b.reshape(shape)
+
+
+def point(n: int, m: int, cfl: float, c: float, u: np.ndarray, ut: np.ndarray, nsteps: int,
+          i: int, j: int, k: int, evolution: str = "taylor", param: int | None = None):
+    """Values (u then u_t, 2*M^3 scaled derivatives) at primal node (i,j,k)
+    after nsteps full steps, from its dependency cone only."""
+    evo, param = _evo(m, evolution, param)
+    a = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
+    b = np.ascontiguousarray(np.asarray(ut, dtype=np.float64).ravel())
+    out = np.zeros(2 * (m + 1) ** 3)
+    rc = load().oracle_point(n, m, float(cfl), float(c), evo, param, int(nsteps),
+                             _ptr(a), _ptr(b), i, j, k, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_point failed: {rc}")
+    return out
