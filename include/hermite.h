@@ -1,0 +1,141 @@
+/*
+ * hermite.h - C ABI of the MI355X (gfx950) Hermite wave solver.
+ *
+ * The library advances the 3D scalar wave equation u_tt = c^2 (u_x1x1 +
+ * u_x2x2 + u_x3x3) on the periodic unit cube [0,1)^3 with the Hermite method
+ * studied by Vargas, Chan, Hagstrom and Warburton, "GPU Acceleration of
+ * Hermite Methods for the Simulation of Wave Propagation" (arXiv:1609.09841).
+ *
+ * Problem statement (Sec. 2): a periodic grid of n cells per side, h = 1/n;
+ * each node carries the scaled derivatives h^{|d|}/d! D^d of u and of u_t for
+ * every multi-index d in [0,m]^3 (Eq. 2; the paper calls m "N"). One full time
+ * step dt = cfl * h / c is two half steps: primal -> dual grid, then dual ->
+ * primal grid (Sec. 2). Each half step builds, on every cell, the tensor
+ * Hermite interpolant of degree 2m+1 per variable from the 8 vertices (Eq. 3;
+ * Sec. 3.1, Alg. 1-2) and evolves it through dt/2 (Sec. 3.2, Alg. 3-4, Taylor
+ * series; or classical 4-stage Runge-Kutta, the multi-stage evolution of the
+ * abstract). The coefficients of the evolved polynomial with every index <= m
+ * are the new data of the node at the cell centre.
+ *
+ * Array layout (Sec. 3.1, the tensor u[m3][m2][m1][n3][n2][n1]): a field
+ * holds (m+1)^3 * n^3 doubles ordered [d3][d2][d1][k][j][i], i (x1) fastest.
+ * Node (i, j, k) is the point (i, j, k) * h.
+ *
+ * Errors: every int-returning call returns HERMITE_OK (0) or a negative
+ * code; no call aborts or throws. On failure nothing is changed. The text of
+ * the last error is returned by hermite_last_error. Device faults of
+ * asynchronous work surface at the next hermite_sync / hermite_gather*.
+ *
+ * Threading: a context may be used by one host thread at a time.
+ */
+#ifndef HERMITE_H
+#define HERMITE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HERMITE_OK 0
+#define HERMITE_EINVAL (-1)       /* bad argument: see each call */
+#define HERMITE_ENOMEM (-2)       /* device allocation failed or size overflow */
+#define HERMITE_EDEVICE (-3)      /* HIP runtime error (no device, launch failure, fault) */
+#define HERMITE_ESTATE (-4)       /* call out of order (step/gather before set_initial) */
+#define HERMITE_EUNSUPPORTED (-5) /* valid but unsupported combination of options */
+
+/* arithmetic of the interpolation/evolution contractions; the nodal state
+ * and the half-step update are FP64 in every mode */
+#define HERMITE_PREC_FP64 0
+#define HERMITE_PREC_FP32 1
+#define HERMITE_PREC_BF16X3 2
+
+#define HERMITE_EVOLVE_TAYLOR 0 /* Sec. 3.2, Alg. 4: q-stage Taylor series (Horner) */
+#define HERMITE_EVOLVE_RK4 1    /* classical 4-stage Runge-Kutta on the cell ODE */
+
+typedef struct hermite_ctx hermite_ctx; /* opaque; owns all device memory */
+
+typedef struct hermite_options {
+    int precision;   /* HERMITE_PREC_*; default FP64 */
+    int evolution;   /* HERMITE_EVOLVE_*; default Taylor */
+    int rk_substeps; /* RK4 substeps per half step, >= 1; 0 -> 1 */
+    int q;           /* Taylor stages, 1..64; 0 -> 6m+1, the exact count for
+                        this system (the paper's d(2N+1) = 6m+3 gives the same
+                        result up to rounding, Sec. 3.2) */
+    int fused;       /* 1: one kernel per half step (Sec. 3.3, monolithic);
+                        0: interpolation and evolution kernels with the
+                        reconstructed coefficients in device memory
+                        (Sec. 3.1-3.2, two kernels) */
+    int poison;      /* debug: 1 fills each destination grid with NaN before
+                        the half step that writes it */
+    void *stream;    /* hipStream_t to run on; NULL -> a stream owned by the
+                        context. Caller keeps a given stream alive until
+                        hermite_destroy. */
+} hermite_options;
+
+/* Fills *opt with the defaults (FP64, Taylor q = 6m+1, fused, own stream). */
+void hermite_default_options(hermite_options *opt);
+
+/*
+ * Creates a solver for n_cells^3 periodic cells of order m (Sec. 2).
+ *   n_cells: cells per side, 2 <= n_cells <= 1290
+ *   m:       derivatives per dimension, 1..3
+ *   cfl:     c*dt/h, 0 < cfl <= 1 and finite. The paper's stability statement
+ *            (Sec. 2: waves must not cross from the cell boundary to its centre
+ *            in a half step) is necessary; in 3D the Taylor method is stable
+ *            up to about 0.8 and RK4 (1 substep) up to 0.5.
+ *   c:       wave speed, > 0 and finite
+ *   opt:     NULL for defaults
+ *   out:     receives the context; untouched on failure
+ * Arguments are validated before any HIP call: invalid arguments return
+ * HERMITE_EINVAL even without a device. Allocates two FP64 grids of
+ * 2*(m+1)^3*n^3 doubles each, plus 2*(2m+2)^3*n^3 doubles when fused == 0.
+ * No kernel runs.
+ */
+int hermite_create(int n_cells, int m, double cfl, double c,
+                   const hermite_options *opt, hermite_ctx **out);
+
+/*
+ * Sets the primal-grid state at t = 0 from host arrays u and ut (scaled
+ * derivatives of u and of u_t, layout above, (m+1)^3*n^3 doubles each; the
+ * caller keeps ownership). Copies synchronously. Resets t and the step count.
+ */
+int hermite_set_initial(hermite_ctx *ctx, const double *u, const double *ut);
+
+/* As hermite_set_initial, from device arrays; stream-ordered on the
+ * context's stream (the caller must not free them before that work ends). */
+int hermite_set_initial_device(hermite_ctx *ctx, const void *u_dev, const void *ut_dev);
+
+/*
+ * Enqueues n_full_steps full steps (2 * n_full_steps half steps) on the
+ * context's stream and returns without waiting. n_full_steps >= 0.
+ * HERMITE_ESTATE before any set_initial.
+ */
+int hermite_step(hermite_ctx *ctx, int n_full_steps);
+
+/*
+ * Waits for the stream, then copies the primal-grid state to host arrays u and
+ * ut (same layout as set_initial) and stores t = steps * dt in *t_out (t_out
+ * may be NULL; u or ut may be NULL to skip that field).
+ */
+int hermite_gather(hermite_ctx *ctx, double *u, double *ut, double *t_out);
+
+/* Stream-ordered copy of the state into device arrays (no host wait). */
+int hermite_gather_device(hermite_ctx *ctx, void *u_dev, void *ut_dev);
+
+/* Waits for all work enqueued on the context's stream. */
+int hermite_sync(hermite_ctx *ctx);
+
+/* Time reached by the enqueued steps, full steps taken, and dt. Any pointer may be NULL. */
+int hermite_get_time(const hermite_ctx *ctx, double *t, long long *steps, double *dt);
+
+/* Waits for outstanding work and frees everything the context owns. NULL is a no-op. */
+void hermite_destroy(hermite_ctx *ctx);
+
+/* Last error text of ctx, or of the calling thread when ctx is NULL
+ * (for failures of hermite_create). Never NULL; "" when there was none. */
+const char *hermite_last_error(const hermite_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HERMITE_H */

@@ -42,6 +42,15 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The oracle computes in FP64. The same source built with
+ * -DORACLE_REAL='long double' gives a twin whose only purpose is to measure
+ * how far FP64 rounding alone moves the FP64 build (the rounding floor that
+ * any FP64 implementation of the method shares). */
+#ifndef ORACLE_REAL
+#define ORACLE_REAL double
+#endif
+typedef ORACLE_REAL real;
+
 #define OR_MAXM 4
 #define OR_MAXP (2 * OR_MAXM + 2)
 
@@ -63,10 +72,10 @@ static long double or_binom(int a, int b)
  * So b = H * data maps the scaled derivatives [L0..Lm, R0..Rm] of the two
  * end nodes to the monomial coefficients b_0..b_{2m+1} about the centre.
  * Gauss-Jordan elimination with partial pivoting in long double, rounded to
- * double at the end. H is row-major, H[j*P + r], r = side*(m+1) + k.
+ * real at the end. H is row-major, H[j*P + r], r = side*(m+1) + k.
  * Returns 0, or -1 for m outside [1, 4].
  */
-int oracle_hermite_matrix(int m, double *H)
+int oracle_hermite_matrix(int m, real *H)
 {
     if (m < 1 || m > OR_MAXM) return -1;
     const int M = m + 1, P = 2 * m + 2;
@@ -104,7 +113,7 @@ int oracle_hermite_matrix(int m, double *H)
     }
     /* A's right half is V^{-1}: rows are coefficient indices j, columns data r */
     for (int j = 0; j < P; ++j)
-        for (int r = 0; r < P; ++r) H[j * P + r] = (double)A[j][P + r];
+        for (int r = 0; r < P; ++r) H[j * P + r] = (real)A[j][P + r];
     return 0;
 }
 
@@ -112,13 +121,13 @@ int oracle_hermite_matrix(int m, double *H)
  * Alg. 1 generalised to any axis: apply the P x P matrix H along one axis of
  * a P^3 tensor T[a3][a2][a1] (a1 fastest). axis 0 is x1, 1 is x2, 2 is x3.
  */
-static void or_apply_axis(int P, const double *H, int axis, const double *in, double *out)
+static void or_apply_axis(int P, const real *H, int axis, const real *in, real *out)
 {
     for (int a3 = 0; a3 < P; ++a3)
         for (int a2 = 0; a2 < P; ++a2)
             for (int a1 = 0; a1 < P; ++a1) {
                 int t = (axis == 0) ? a1 : (axis == 1) ? a2 : a3;
-                double c = 0.0;
+                real c = 0.0;
                 for (int k = 0; k < P; ++k) {
                     int b1 = a1, b2 = a2, b3 = a3;
                     if (axis == 0) b1 = k;
@@ -136,10 +145,10 @@ static void or_apply_axis(int P, const double *H, int axis, const double *in, do
  * order per axis; R receives the monomial coefficients R[j3][j2][j1] of the
  * interpolant in xi (Eq. 3).
  */
-void oracle_interpolate_cell(int m, const double *H, const double *uloc, double *R)
+void oracle_interpolate_cell(int m, const real *H, const real *uloc, real *R)
 {
     const int P = 2 * m + 2;
-    double t1[OR_MAXP * OR_MAXP * OR_MAXP], t2[OR_MAXP * OR_MAXP * OR_MAXP];
+    real t1[OR_MAXP * OR_MAXP * OR_MAXP], t2[OR_MAXP * OR_MAXP * OR_MAXP];
     or_apply_axis(P, H, 0, uloc, t1);
     or_apply_axis(P, H, 1, t1, t2);
     or_apply_axis(P, H, 2, t2, R);
@@ -149,29 +158,29 @@ void oracle_interpolate_cell(int m, const double *H, const double *uloc, double 
  * Alg. 3 in the cell variable xi (h = 1 there): differentiate the coefficient
  * tensor along one axis, (D W)[j] = (j+1) W[j+1], zero at the top index.
  */
-static void or_diff_axis(int P, int axis, const double *W, double *out)
+static void or_diff_axis(int P, int axis, const real *W, real *out)
 {
     for (int j3 = 0; j3 < P; ++j3)
         for (int j2 = 0; j2 < P; ++j2)
             for (int j1 = 0; j1 < P; ++j1) {
                 int t = (axis == 0) ? j1 : (axis == 1) ? j2 : j3;
-                double v = 0.0;
+                real v = 0.0;
                 if (t < P - 1) {
                     int b1 = j1, b2 = j2, b3 = j3;
                     if (axis == 0) b1 = t + 1;
                     else if (axis == 1) b2 = t + 1;
                     else b3 = t + 1;
-                    v = (double)(t + 1) * W[(b3 * P + b2) * P + b1];
+                    v = (real)(t + 1) * W[(b3 * P + b2) * P + b1];
                 }
                 out[(j3 * P + j2) * P + j1] = v;
             }
 }
 
 /* Laplacian in xi: sum over axes of Alg. 3 applied twice. */
-void oracle_laplacian(int m, const double *W, double *out)
+void oracle_laplacian(int m, const real *W, real *out)
 {
     const int P = 2 * m + 2, n3 = P * P * P;
-    double d1[OR_MAXP * OR_MAXP * OR_MAXP], d2[OR_MAXP * OR_MAXP * OR_MAXP];
+    real d1[OR_MAXP * OR_MAXP * OR_MAXP], d2[OR_MAXP * OR_MAXP * OR_MAXP];
     for (int t = 0; t < n3; ++t) out[t] = 0.0;
     for (int axis = 0; axis < 3; ++axis) {
         or_diff_axis(P, axis, W, d1);
@@ -181,7 +190,7 @@ void oracle_laplacian(int m, const double *W, double *out)
 }
 
 /* The cell operator of the first-order system: L(a, b) = lam * (b, Lap a). */
-static void or_apply_L(int m, double lam, const double *a, const double *b, double *la, double *lb)
+static void or_apply_L(int m, real lam, const real *a, const real *b, real *la, real *lb)
 {
     const int P = 2 * m + 2, n3 = P * P * P;
     oracle_laplacian(m, a, lb);
@@ -197,37 +206,37 @@ static void or_apply_L(int m, double lam, const double *a, const double *b, doub
  * i.e. (Wu, Wv) <- (Ru + (lam/k) Wv, Rv + (lam/k) Lap Wu), both from the old W.
  * Ru, Rv are overwritten with the evolved coefficients at sigma = 1.
  */
-void oracle_evolve_taylor(int m, int q, double lam, double *Ru, double *Rv)
+void oracle_evolve_taylor(int m, int q, real lam, real *Ru, real *Rv)
 {
     const int P = 2 * m + 2, n3 = P * P * P;
-    double wu[OR_MAXP * OR_MAXP * OR_MAXP], wv[OR_MAXP * OR_MAXP * OR_MAXP];
-    double lu[OR_MAXP * OR_MAXP * OR_MAXP], lv[OR_MAXP * OR_MAXP * OR_MAXP];
-    memcpy(wu, Ru, sizeof(double) * n3);
-    memcpy(wv, Rv, sizeof(double) * n3);
+    real wu[OR_MAXP * OR_MAXP * OR_MAXP], wv[OR_MAXP * OR_MAXP * OR_MAXP];
+    real lu[OR_MAXP * OR_MAXP * OR_MAXP], lv[OR_MAXP * OR_MAXP * OR_MAXP];
+    memcpy(wu, Ru, sizeof(real) * n3);
+    memcpy(wv, Rv, sizeof(real) * n3);
     for (int k = q; k >= 1; --k) {
         or_apply_L(m, lam, wu, wv, lu, lv);
         for (int t = 0; t < n3; ++t) {
-            wu[t] = Ru[t] + lu[t] / (double)k;
-            wv[t] = Rv[t] + lv[t] / (double)k;
+            wu[t] = Ru[t] + lu[t] / (real)k;
+            wv[t] = Rv[t] + lv[t] / (real)k;
         }
     }
-    memcpy(Ru, wu, sizeof(double) * n3);
-    memcpy(Rv, wv, sizeof(double) * n3);
+    memcpy(Ru, wu, sizeof(real) * n3);
+    memcpy(Rv, wv, sizeof(real) * n3);
 }
 
 /*
  * Classical 4-stage Runge-Kutta on dW/dsigma = L W over sigma in [0, 1] with
  * S equal substeps (the abstract's multi-stage local evolution).
  */
-void oracle_evolve_rk4(int m, int S, double lam, double *Ru, double *Rv)
+void oracle_evolve_rk4(int m, int S, real lam, real *Ru, real *Rv)
 {
     const int P = 2 * m + 2, n3 = P * P * P;
-    const double dl = 1.0 / (double)S;
-    double k1u[OR_MAXP * OR_MAXP * OR_MAXP], k1v[OR_MAXP * OR_MAXP * OR_MAXP];
-    double k2u[OR_MAXP * OR_MAXP * OR_MAXP], k2v[OR_MAXP * OR_MAXP * OR_MAXP];
-    double k3u[OR_MAXP * OR_MAXP * OR_MAXP], k3v[OR_MAXP * OR_MAXP * OR_MAXP];
-    double k4u[OR_MAXP * OR_MAXP * OR_MAXP], k4v[OR_MAXP * OR_MAXP * OR_MAXP];
-    double yu[OR_MAXP * OR_MAXP * OR_MAXP], yv[OR_MAXP * OR_MAXP * OR_MAXP];
+    const real dl = 1.0 / (real)S;
+    real k1u[OR_MAXP * OR_MAXP * OR_MAXP], k1v[OR_MAXP * OR_MAXP * OR_MAXP];
+    real k2u[OR_MAXP * OR_MAXP * OR_MAXP], k2v[OR_MAXP * OR_MAXP * OR_MAXP];
+    real k3u[OR_MAXP * OR_MAXP * OR_MAXP], k3v[OR_MAXP * OR_MAXP * OR_MAXP];
+    real k4u[OR_MAXP * OR_MAXP * OR_MAXP], k4v[OR_MAXP * OR_MAXP * OR_MAXP];
+    real yu[OR_MAXP * OR_MAXP * OR_MAXP], yv[OR_MAXP * OR_MAXP * OR_MAXP];
     for (int s = 0; s < S; ++s) {
         or_apply_L(m, lam, Ru, Rv, k1u, k1v);
         for (int t = 0; t < n3; ++t) { yu[t] = Ru[t] + 0.5 * dl * k1u[t]; yv[t] = Rv[t] + 0.5 * dl * k1v[t]; }
@@ -248,7 +257,7 @@ void oracle_evolve_rk4(int m, int S, double lam, double *Ru, double *Rv)
  * a periodic grid field g[d3][d2][d1][k][j][i] (Sec. 3.1: the (m+1)^3 values
  * of each of the 8 vertices). uloc[a3][a2][a1], a = side*(m+1) + d.
  */
-void oracle_gather_cell(int n, int m, const double *g, int i, int j, int k, double *uloc)
+void oracle_gather_cell(int n, int m, const real *g, int i, int j, int k, real *uloc)
 {
     const int M = m + 1, P = 2 * M;
     const long nn = (long)n * n * n;
@@ -267,7 +276,7 @@ void oracle_gather_cell(int n, int m, const double *g, int i, int j, int k, doub
 }
 
 /* evo: 0 = Taylor (param = q), 1 = RK4 (param = substeps S) */
-static void or_evolve(int m, int evo, int param, double lam, double *Ru, double *Rv)
+static void or_evolve(int m, int evo, int param, real lam, real *Ru, real *Rv)
 {
     if (evo == 0) oracle_evolve_taylor(m, param, lam, Ru, Rv);
     else oracle_evolve_rk4(m, param, lam, Ru, Rv);
@@ -282,8 +291,8 @@ static void or_evolve(int m, int evo, int param, double lam, double *Ru, double 
  * corner (i,j,k) writes dual (i,j,k); to_dual = 0: dual -> primal, writes
  * primal (i+1, j+1, k+1) mod n.
  */
-void oracle_half_step(int n, int m, const double *H, double lam, int evo, int param,
-                      const double *src, double *dst, int to_dual)
+void oracle_half_step(int n, int m, const real *H, real lam, int evo, int param,
+                      const real *src, real *dst, int to_dual)
 {
     const int M = m + 1, P = 2 * M, M3 = M * M * M;
     const long nn = (long)n * n * n;
@@ -291,8 +300,8 @@ void oracle_half_step(int n, int m, const double *H, double lam, int evo, int pa
 #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < n; ++k)
         for (int j = 0; j < n; ++j) {
-            double uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
-            double Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
+            real uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
+            real Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
             for (int i = 0; i < n; ++i) {
                 oracle_gather_cell(n, m, src, i, j, k, uloc);
                 oracle_gather_cell(n, m, src + (long)M3 * nn, i, j, k, vloc);
@@ -317,20 +326,20 @@ void oracle_half_step(int n, int m, const double *H, double lam, int evo, int pa
  * each [M^3][n^3]) are advanced by nsteps full steps in place. dt = cfl*h/c,
  * tau = dt/2, lam = c*tau/h. Returns 0, or a negative value on bad input.
  */
-int oracle_run(int n, int m, double cfl, double c, int evo, int param, int nsteps,
-               double *u, double *ut)
+int oracle_run(int n, int m, real cfl, real c, int evo, int param, int nsteps,
+               real *u, real *ut)
 {
     if (n < 1 || m < 1 || m > OR_MAXM || !(cfl > 0.0) || !(c > 0.0) || nsteps < 0 || param < 1)
         return -1;
     const int M = m + 1, P = 2 * M, M3 = M * M * M;
     const long nn = (long)n * n * n, sz = (long)M3 * nn;
-    const double h = 1.0 / (double)n;
-    const double dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
-    double H[OR_MAXP * OR_MAXP];
+    const real h = 1.0 / (real)n;
+    const real dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    real H[OR_MAXP * OR_MAXP];
     if (oracle_hermite_matrix(m, H) != 0) return -2;
     (void)P;
-    double *a = (double *)malloc(sizeof(double) * 2 * sz);
-    double *b = (double *)malloc(sizeof(double) * 2 * sz);
+    real *a = (real *)malloc(sizeof(real) * 2 * sz);
+    real *b = (real *)malloc(sizeof(real) * 2 * sz);
     if (!a || !b) { free(a); free(b); return -3; }
     for (long t = 0; t < sz; ++t) { a[t] = u[t]; a[sz + t] = (h / c) * ut[t]; }
     for (int s = 0; s < nsteps; ++s) {
@@ -345,47 +354,40 @@ int oracle_run(int n, int m, double cfl, double c, int evo, int param, int nstep
 
 /*
  * Local (non-periodic) dependency cone of one primal node after nsteps full
- * steps, for sampled checks of large grids: the node (i0, j0, k0) after
- * nsteps full steps depends only on the (2*nsteps+1)^3 primal nodes around
- * it. Runs the same cell algorithm on that box (with periodic wrap of the
- * source indices) and returns the node's 2*M^3 values, u then u_t.
+ * steps, for sampled checks of large grids: the node after nsteps full steps
+ * depends only on the w^3 primal nodes around it, w = 2*nsteps+1. box and
+ * vbox hold those nodes of u and u_t, laid out [d3][d2][d1][z][y][x] with the
+ * target node at the centre (x = y = z = nsteps). n sets h = 1/n. Runs the
+ * same cell algorithm on the shrinking box and returns the node's 2*M^3
+ * values, u then u_t.
  */
-int oracle_point(int n, int m, double cfl, double c, int evo, int param, int nsteps,
-                 const double *u, const double *ut, int i0, int j0, int k0, double *out)
+int oracle_point_box(int n, int m, real cfl, real c, int evo, int param, int nsteps,
+                     const real *ubox, const real *utbox, real *out)
 {
     if (n < 1 || m < 1 || m > OR_MAXM || nsteps < 1 || param < 1) return -1;
     const int M = m + 1, P = 2 * M, M3 = M * M * M;
-    const long nn = (long)n * n * n;
-    const double h = 1.0 / (double)n;
-    const double dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
-    double H[OR_MAXP * OR_MAXP];
+    const real h = 1.0 / (real)n;
+    const real dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    real H[OR_MAXP * OR_MAXP];
     if (oracle_hermite_matrix(m, H) != 0) return -2;
-    /* box of primal nodes i0-s .. i0+s; box side w shrinks by one per half step */
     int w = 2 * nsteps + 1;
-    double *box = (double *)malloc(sizeof(double) * 2 * M3 * (long)w * w * w);
+    const long w3 = (long)w * w * w;
+    real *box = (real *)malloc(sizeof(real) * 2 * M3 * w3);
     if (!box) return -3;
-    for (int f = 0; f < 2; ++f)
-        for (int dd = 0; dd < M3; ++dd)
-            for (int z = 0; z < w; ++z)
-                for (int y = 0; y < w; ++y)
-                    for (int x = 0; x < w; ++x) {
-                        int gi = ((i0 - nsteps + x) % n + n) % n;
-                        int gj = ((j0 - nsteps + y) % n + n) % n;
-                        int gk = ((k0 - nsteps + z) % n + n) % n;
-                        double v = (f == 0 ? u : ut)[(long)dd * nn + ((long)gk * n + gj) * n + gi];
-                        if (f == 1) v *= h / c;
-                        box[(((long)(f * M3 + dd) * w + z) * w + y) * w + x] = v;
-                    }
+    for (long t = 0; t < (long)M3 * w3; ++t) {
+        box[t] = ubox[t];
+        box[(long)M3 * w3 + t] = (h / c) * utbox[t];
+    }
     for (int hs = 0; hs < 2 * nsteps; ++hs) {
         const int wn = w - 1;
-        double *nb = (double *)malloc(sizeof(double) * 2 * M3 * (long)wn * wn * wn);
+        real *nb = (real *)malloc(sizeof(real) * 2 * M3 * (long)wn * wn * wn);
         if (!nb) { free(box); return -3; }
         for (int z = 0; z < wn; ++z)
             for (int y = 0; y < wn; ++y)
                 for (int x = 0; x < wn; ++x) {
-                    double uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
+                    real uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
                     for (int f = 0; f < 2; ++f) {
-                        double *loc = f ? vloc : uloc;
+                        real *loc = f ? vloc : uloc;
                         for (int s3 = 0; s3 < 2; ++s3)
                             for (int s2 = 0; s2 < 2; ++s2)
                                 for (int s1 = 0; s1 < 2; ++s1)
@@ -397,7 +399,7 @@ int oracle_point(int n, int m, double cfl, double c, int evo, int param, int nst
                                                 loc[((s3 * M + d3) * P + s2 * M + d2) * P + s1 * M + d1] = box[sidx];
                                             }
                     }
-                    double Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
+                    real Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
                     oracle_interpolate_cell(m, H, uloc, Ru);
                     oracle_interpolate_cell(m, H, vloc, Rv);
                     or_evolve(m, evo, param, lam, Ru, Rv);
@@ -413,11 +415,42 @@ int oracle_point(int n, int m, double cfl, double c, int evo, int param, int nst
         box = nb;
         w = wn;
     }
-    /* w == 1: the remaining node is primal (i0, j0, k0) */
+    /* w == 1: the remaining node is the target primal node */
     for (int dd = 0; dd < M3; ++dd) {
         out[dd] = box[dd];
         out[M3 + dd] = (c / h) * box[M3 + dd];
     }
     free(box);
     return 0;
+}
+
+/* oracle_point_box on a full periodic grid: extracts the box around primal
+ * node (i0, j0, k0) (periodic wrap) and runs it. */
+int oracle_point(int n, int m, real cfl, real c, int evo, int param, int nsteps,
+                 const real *u, const real *ut, int i0, int j0, int k0, real *out)
+{
+    if (n < 1 || m < 1 || m > OR_MAXM || nsteps < 1 || param < 1) return -1;
+    const int M = m + 1, M3 = M * M * M;
+    const long nn = (long)n * n * n;
+    const int w = 2 * nsteps + 1;
+    const long w3 = (long)w * w * w;
+    real *ub = (real *)malloc(sizeof(real) * M3 * w3);
+    real *vb = (real *)malloc(sizeof(real) * M3 * w3);
+    if (!ub || !vb) { free(ub); free(vb); return -3; }
+    for (int dd = 0; dd < M3; ++dd)
+        for (int z = 0; z < w; ++z)
+            for (int y = 0; y < w; ++y)
+                for (int x = 0; x < w; ++x) {
+                    int gi = ((i0 - nsteps + x) % n + n) % n;
+                    int gj = ((j0 - nsteps + y) % n + n) % n;
+                    int gk = ((k0 - nsteps + z) % n + n) % n;
+                    long g = (long)dd * nn + ((long)gk * n + gj) * n + gi;
+                    long b = (((long)dd * w + z) * w + y) * w + x;
+                    ub[b] = u[g];
+                    vb[b] = ut[g];
+                }
+    int rc = oracle_point_box(n, m, cfl, c, evo, param, nsteps, ub, vb, out);
+    free(ub);
+    free(vb);
+    return rc;
 }

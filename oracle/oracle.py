@@ -19,35 +19,42 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hermite_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_LD_PATH = os.path.join(_HERE, "liboracle_ld.so")
 _lib = None
+_lib_ld = None
 
 __all__ = [
     "build_oracle", "load", "exact_hermite_matrix", "hermite_matrix",
     "interpolate_cell", "laplacian", "evolve_taylor", "evolve_rk4",
-    "gather_cell", "half_step", "run", "point", "exact_q",
+    "gather_cell", "half_step", "run", "point", "point_box", "exact_q",
 ]
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile the C oracle with gcc (plain -O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB_PATH)
+    """Compile the C oracle with gcc (plain -O2, OpenMP, no fast-math), and its
+    long-double twin used only to measure the FP64 rounding floor."""
+    for path, extra in ((_LIB_PATH, []), (_LIB_LD_PATH, ["-DORACLE_REAL=long double"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                   "-ffp-contract=off", *extra, "-o", tmp, _SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
-def load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
+def load(ld: bool = False):
+    """The FP64 oracle library, or (ld=True) its long-double twin."""
+    global _lib, _lib_ld
+    if (_lib_ld if ld else _lib) is not None:
+        return _lib_ld if ld else _lib
+    path = _LIB_LD_PATH if ld else _LIB_PATH
+    if not os.path.exists(path):
         build_oracle(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
-    dp = ctypes.POINTER(ctypes.c_double)
-    i, d = ctypes.c_int, ctypes.c_double
+    lib = ctypes.CDLL(path)
+    real = ctypes.c_longdouble if ld else ctypes.c_double
+    dp = ctypes.POINTER(real)
+    i, d = ctypes.c_int, real
     lib.oracle_hermite_matrix.argtypes = [i, dp]
     lib.oracle_hermite_matrix.restype = i
     lib.oracle_interpolate_cell.argtypes = [i, dp, dp, dp]
@@ -66,12 +73,20 @@ def load():
     lib.oracle_run.restype = i
     lib.oracle_point.argtypes = [i, i, d, d, i, i, i, dp, dp, i, i, i, dp]
     lib.oracle_point.restype = i
-    _lib = lib
+    lib.oracle_point_box.argtypes = [i, i, d, d, i, i, i, dp, dp, dp]
+    lib.oracle_point_box.restype = i
+    if ld:
+        _lib_ld = lib
+    else:
+        _lib = lib
     return lib
 
 
 def _ptr(a: np.ndarray):
-    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    assert a.flags["C_CONTIGUOUS"]
+    if a.dtype == np.longdouble and np.longdouble != np.float64:
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longdouble))
+    assert a.dtype == np.float64
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
@@ -193,20 +208,22 @@ def _evo(m, evolution, param):
 
 
 def run(n: int, m: int, cfl: float, c: float, u: np.ndarray, ut: np.ndarray, nsteps: int,
-        evolution: str = "taylor", param: int | None = None):
+        evolution: str = "taylor", param: int | None = None, ld: bool = False):
     """Advance primal-grid scaled derivatives (u, u_t), each [M^3][n^3] (any
     shape with that many elements, layout [d3][d2][d1][k][j][i]), by nsteps
-    full steps. Returns new (u, ut) arrays of the same shape."""
+    full steps. Returns new (u, ut) float64 arrays of the same shape.
+    ld=True runs the long-double twin (rounding-floor measurements only)."""
     evo, param = _evo(m, evolution, param)
     shape = np.shape(u)
-    a = np.array(u, dtype=np.float64).ravel().copy()
-    b = np.array(ut, dtype=np.float64).ravel().copy()
+    dt = np.longdouble if ld else np.float64
+    a = np.array(u, dtype=np.float64).astype(dt).ravel().copy()
+    b = np.array(ut, dtype=np.float64).astype(dt).ravel().copy()
     M3 = (m + 1) ** 3
     assert a.size == M3 * n ** 3 and b.size == a.size
-    rc = load().oracle_run(n, m, float(cfl), float(c), evo, param, int(nsteps), _ptr(a), _ptr(b))
+    rc = load(ld).oracle_run(n, m, float(cfl), float(c), evo, param, int(nsteps), _ptr(a), _ptr(b))
     if rc != 0:
         raise ValueError(f"oracle_run failed: {rc}")
-    return a.reshape(shape), b.reshape(shape)
+    return a.astype(np.float64).reshape(shape), b.astype(np.float64).reshape(shape)
 
 
 def point(n: int, m: int, cfl: float, c: float, u: np.ndarray, ut: np.ndarray, nsteps: int,
@@ -221,4 +238,22 @@ def point(n: int, m: int, cfl: float, c: float, u: np.ndarray, ut: np.ndarray, n
                              _ptr(a), _ptr(b), i, j, k, _ptr(out))
     if rc != 0:
         raise ValueError(f"oracle_point failed: {rc}")
+    return out
+
+
+def point_box(n: int, m: int, cfl: float, c: float, ubox: np.ndarray, utbox: np.ndarray, nsteps: int,
+              evolution: str = "taylor", param: int | None = None):
+    """Values (u then u_t) at the centre primal node of a (2*nsteps+1)^3 box of
+    primal nodes, laid out [M^3][w][w][w], after nsteps full steps (grid of n
+    cells per side, so h = 1/n)."""
+    evo, param = _evo(m, evolution, param)
+    a = np.ascontiguousarray(np.asarray(ubox, dtype=np.float64).ravel())
+    b = np.ascontiguousarray(np.asarray(utbox, dtype=np.float64).ravel())
+    w = 2 * nsteps + 1
+    assert a.size == (m + 1) ** 3 * w ** 3 and b.size == a.size
+    out = np.zeros(2 * (m + 1) ** 3)
+    rc = load().oracle_point_box(n, m, float(cfl), float(c), evo, param, int(nsteps),
+                                 _ptr(a), _ptr(b), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_point_box failed: {rc}")
     return out

@@ -1,0 +1,213 @@
+"""ctypes binding of libhermite.so (the C ABI in include/hermite.h).
+
+Argument marshalling only: every step of the half step runs in the library's
+HIP kernels. Loading fails loudly when the library is missing; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhermite.so")
+
+HERMITE_OK = 0
+HERMITE_EINVAL = -1
+HERMITE_ENOMEM = -2
+HERMITE_EDEVICE = -3
+HERMITE_ESTATE = -4
+HERMITE_EUNSUPPORTED = -5
+
+HERMITE_PREC_FP64 = 0
+HERMITE_PREC_FP32 = 1
+HERMITE_PREC_BF16X3 = 2
+HERMITE_EVOLVE_TAYLOR = 0
+HERMITE_EVOLVE_RK4 = 1
+
+PRECISIONS = {"fp64": HERMITE_PREC_FP64, "fp32": HERMITE_PREC_FP32, "bf16x3": HERMITE_PREC_BF16X3}
+EVOLUTIONS = {"taylor": HERMITE_EVOLVE_TAYLOR, "rk4": HERMITE_EVOLVE_RK4}
+
+# every symbol include/hermite.h declares
+EXPORTS = (
+    "hermite_default_options", "hermite_create", "hermite_set_initial", "hermite_set_initial_device",
+    "hermite_step", "hermite_gather", "hermite_gather_device", "hermite_sync", "hermite_get_time",
+    "hermite_destroy", "hermite_last_error",
+)
+
+
+class hermite_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("evolution", ctypes.c_int),
+        ("rk_substeps", ctypes.c_int),
+        ("q", ctypes.c_int),
+        ("fused", ctypes.c_int),
+        ("poison", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class HermiteError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hermite error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhermite.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1609_09841_amd.build.build() "
+                          "(the HIP library is required; there is no fallback)")
+    lib = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    opt_p = ctypes.POINTER(hermite_options)
+    lib.hermite_default_options.argtypes = [opt_p]
+    lib.hermite_default_options.restype = None
+    lib.hermite_create.argtypes = [ip, ip, ctypes.c_double, ctypes.c_double, opt_p, ctypes.POINTER(vp)]
+    lib.hermite_create.restype = ip
+    lib.hermite_set_initial.argtypes = [vp, dp, dp]
+    lib.hermite_set_initial.restype = ip
+    lib.hermite_set_initial_device.argtypes = [vp, vp, vp]
+    lib.hermite_set_initial_device.restype = ip
+    lib.hermite_step.argtypes = [vp, ip]
+    lib.hermite_step.restype = ip
+    lib.hermite_gather.argtypes = [vp, dp, dp, dp]
+    lib.hermite_gather.restype = ip
+    lib.hermite_gather_device.argtypes = [vp, vp, vp]
+    lib.hermite_gather_device.restype = ip
+    lib.hermite_sync.argtypes = [vp]
+    lib.hermite_sync.restype = ip
+    lib.hermite_get_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), dp]
+    lib.hermite_get_time.restype = ip
+    lib.hermite_destroy.argtypes = [vp]
+    lib.hermite_destroy.restype = None
+    lib.hermite_last_error.argtypes = [vp]
+    lib.hermite_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != HERMITE_OK:
+        msg = load().hermite_last_error(ctx).decode(errors="replace")
+        raise HermiteError(rc, msg)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# --- functions with the C names (thin wrappers returning status codes) -----
+
+def hermite_default_options() -> hermite_options:
+    o = hermite_options()
+    load().hermite_default_options(ctypes.byref(o))
+    return o
+
+
+def hermite_create(n_cells: int, m: int, cfl: float, c: float, opt: hermite_options | None = None):
+    """Returns (status, ctx handle or None)."""
+    h = ctypes.c_void_p()
+    rc = load().hermite_create(int(n_cells), int(m), float(cfl), float(c),
+                               ctypes.byref(opt) if opt is not None else None, ctypes.byref(h))
+    return rc, (h if rc == HERMITE_OK else None)
+
+
+def hermite_last_error(ctx=None) -> str:
+    return load().hermite_last_error(ctx).decode(errors="replace")
+
+
+# --- a small owning wrapper ------------------------------------------------
+
+class Solver:
+    """One hermite_ctx. Host arrays are numpy float64 of shape
+    (M, M, M, n, n, n) or flat; device arrays are torch CUDA float64 tensors."""
+
+    def __init__(self, n: int, m: int, cfl: float = 0.5, c: float = 1.0, *, precision: str = "fp64",
+                 evolution: str = "taylor", q: int = 0, rk_substeps: int = 1, fused: bool = True,
+                 poison: bool = False, stream=None):
+        lib = load()
+        o = hermite_default_options()
+        o.precision = PRECISIONS[precision]
+        o.evolution = EVOLUTIONS[evolution]
+        o.q = int(q)
+        o.rk_substeps = int(rk_substeps)
+        o.fused = int(bool(fused))
+        o.poison = int(bool(poison))
+        if stream is not None:
+            o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self.n, self.m = int(n), int(m)
+        self.M3 = (self.m + 1) ** 3
+        self.size = self.M3 * self.n ** 3
+        self._stream = stream
+        rc, h = hermite_create(n, m, cfl, c, o)
+        _check(rc, None)
+        self._ctx = h
+        self._lib = lib
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def set_initial(self, u, ut):
+        if hasattr(u, "is_cuda") and u.is_cuda:
+            assert u.dtype == ut.dtype and str(u.dtype) == "torch.float64"
+            assert u.is_contiguous() and ut.is_contiguous() and u.numel() == self.size == ut.numel()
+            _check(self._lib.hermite_set_initial_device(self._ctx, ctypes.c_void_p(u.data_ptr()),
+                                                        ctypes.c_void_p(ut.data_ptr())), self._ctx)
+            return
+        a = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        b = np.ascontiguousarray(np.asarray(ut, dtype=np.float64)).ravel()
+        assert a.size == self.size and b.size == self.size
+        _check(self._lib.hermite_set_initial(self._ctx, _dptr(a), _dptr(b)), self._ctx)
+
+    def step(self, nsteps: int = 1):
+        _check(self._lib.hermite_step(self._ctx, int(nsteps)), self._ctx)
+
+    def sync(self):
+        _check(self._lib.hermite_sync(self._ctx), self._ctx)
+
+    def gather(self):
+        """(u, ut, t) as numpy arrays shaped (M, M, M, n, n, n)."""
+        M, n = self.m + 1, self.n
+        u = np.empty((M, M, M, n, n, n))
+        ut = np.empty_like(u)
+        t = ctypes.c_double()
+        _check(self._lib.hermite_gather(self._ctx, _dptr(u), _dptr(ut), ctypes.byref(t)), self._ctx)
+        return u, ut, t.value
+
+    def gather_device(self, u, ut):
+        assert u.is_cuda and ut.is_cuda and u.numel() == self.size == ut.numel()
+        _check(self._lib.hermite_gather_device(self._ctx, ctypes.c_void_p(u.data_ptr()),
+                                               ctypes.c_void_p(ut.data_ptr())), self._ctx)
+
+    def time(self):
+        t, s, dt = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        _check(self._lib.hermite_get_time(self._ctx, ctypes.byref(t), ctypes.byref(s), ctypes.byref(dt)), self._ctx)
+        return t.value, s.value, dt.value
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            self._lib.hermite_destroy(self._ctx)
+            self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

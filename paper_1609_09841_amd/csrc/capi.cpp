@@ -1,0 +1,307 @@
+// C ABI of the Hermite wave solver (declared in include/hermite.h).
+//
+// A context owns two FP64 two-field grids (primal, dual), the operator tables
+// and, for the two-kernel variant, the reconstructed-coefficient scratch. One
+// full step enqueues two half steps, primal -> dual and dual -> primal
+// (Sec. 2), on the context's stream; nothing waits on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hermite.h"
+#include "constants.h"
+#include "kernels.h"
+
+struct hermite_ctx {
+    int n = 0, m = 0, M3 = 0;
+    double cfl = 0, c = 0, h = 0, dt = 0, tau = 0, lam = 0;
+    hermite_options opt{};
+    int q = 0, substeps = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    bool use_mfma = false;
+    double* grid[2] = {nullptr, nullptr};  // primal, dual: [2][M^3][n^3] each
+    double* R = nullptr;                   // two-kernel scratch [2][P^3][n^3]
+    double* K = nullptr;                   // fused class operators
+    double* Hp = nullptr;                  // parity blocks of H
+    size_t grid_doubles = 0;
+    bool has_state = false;
+    long long steps = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(hermite_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_err = buf;
+    return code;
+}
+
+int hip_fail(hermite_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, (e == hipErrorOutOfMemory) ? HERMITE_ENOMEM : HERMITE_EDEVICE, "%s: %s (%d)", what,
+                hipGetErrorString(e), (int)e);
+}
+
+#define HCHECK(ctx, expr, what)                          \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+void free_all(hermite_ctx* ctx) {
+    for (double*& g : ctx->grid)
+        if (g) { (void)hipFree(g); g = nullptr; }
+    if (ctx->R) { (void)hipFree(ctx->R); ctx->R = nullptr; }
+    if (ctx->K) { (void)hipFree(ctx->K); ctx->K = nullptr; }
+    if (ctx->Hp) { (void)hipFree(ctx->Hp); ctx->Hp = nullptr; }
+    if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
+}
+
+int select_device(hermite_ctx* ctx) {
+    HCHECK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return HERMITE_OK;
+}
+
+int half_step(hermite_ctx* ctx, int from) {
+    const double* src = ctx->grid[from];
+    double* dst = ctx->grid[1 - from];
+    const int off = from;  // primal -> dual keeps the index, dual -> primal adds one
+    if (ctx->opt.poison)
+        HCHECK(ctx, hipMemsetAsync(dst, 0xFF, ctx->grid_doubles * sizeof(double), ctx->stream), "poison");
+    hipError_t e;
+    if (ctx->opt.fused) {
+        e = hermite::launch_fused(ctx->m, src, dst, ctx->K, ctx->n, off, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "fused half-step launch");
+    } else {
+        e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "interpolation launch");
+        e = hermite::launch_evolve(ctx->m, ctx->R, dst, ctx->n, off, ctx->opt.evolution, ctx->q, ctx->substeps,
+                                   ctx->lam, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "evolution launch");
+    }
+    return HERMITE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hermite_default_options(hermite_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = HERMITE_PREC_FP64;
+    opt->evolution = HERMITE_EVOLVE_TAYLOR;
+    opt->rk_substeps = 1;
+    opt->q = 0;
+    opt->fused = 1;
+    opt->poison = 0;
+    opt->stream = nullptr;
+}
+
+int hermite_create(int n_cells, int m, double cfl, double c, const hermite_options* opt, hermite_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(nullptr, HERMITE_EINVAL, "out is NULL");
+    if (n_cells < 2 || n_cells > 1290) return fail(nullptr, HERMITE_EINVAL, "n_cells=%d outside [2, 1290]", n_cells);
+    if (m < 1 || m > 3) return fail(nullptr, HERMITE_EINVAL, "m=%d outside [1, 3]", m);
+    if (!std::isfinite(cfl) || !(cfl > 0.0) || cfl > 1.0)
+        return fail(nullptr, HERMITE_EINVAL, "cfl=%g outside (0, 1]", cfl);
+    if (!std::isfinite(c) || !(c > 0.0)) return fail(nullptr, HERMITE_EINVAL, "c=%g must be finite and > 0", c);
+    hermite_options o;
+    hermite_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision < 0 || o.precision > 2) return fail(nullptr, HERMITE_EINVAL, "precision=%d", o.precision);
+    if (o.evolution != 0 && o.evolution != 1) return fail(nullptr, HERMITE_EINVAL, "evolution=%d", o.evolution);
+    if (o.rk_substeps < 0 || o.rk_substeps > 64) return fail(nullptr, HERMITE_EINVAL, "rk_substeps=%d", o.rk_substeps);
+    if (o.q < 0 || o.q > 64) return fail(nullptr, HERMITE_EINVAL, "q=%d outside [0, 64]", o.q);
+    if (o.fused != 0 && o.fused != 1) return fail(nullptr, HERMITE_EINVAL, "fused=%d", o.fused);
+    if (o.poison != 0 && o.poison != 1) return fail(nullptr, HERMITE_EINVAL, "poison=%d", o.poison);
+    if (o.precision != HERMITE_PREC_FP64)
+        return fail(nullptr, HERMITE_EUNSUPPORTED, "precision=%d is not available in this build", o.precision);
+
+    const int M = m + 1, P = 2 * m + 2;
+    const size_t nn = (size_t)n_cells * n_cells * n_cells;
+    const size_t grid_doubles = (size_t)2 * M * M * M * nn;
+    const size_t r_doubles = o.fused ? 0 : (size_t)2 * P * P * P * nn;
+
+    hermite_ctx* ctx = new (std::nothrow) hermite_ctx();
+    if (!ctx) return fail(nullptr, HERMITE_ENOMEM, "host allocation failed");
+    ctx->n = n_cells;
+    ctx->m = m;
+    ctx->M3 = M * M * M;
+    ctx->cfl = cfl;
+    ctx->c = c;
+    ctx->h = 1.0 / n_cells;
+    ctx->dt = cfl * ctx->h / c;
+    ctx->tau = 0.5 * ctx->dt;
+    ctx->lam = c * ctx->tau / ctx->h;
+    ctx->opt = o;
+    ctx->q = o.q ? o.q : 6 * m + 1;
+    ctx->substeps = o.rk_substeps ? o.rk_substeps : 1;
+    ctx->grid_doubles = grid_doubles;
+
+    auto bail = [&](int code) {
+        g_err = ctx->err;
+        free_all(ctx);
+        delete ctx;
+        return code;
+    };
+    int rc = HERMITE_OK;
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipGetDevice"));
+    if ((rc = select_device(ctx)) != HERMITE_OK) return bail(rc);
+    if (o.stream) {
+        ctx->stream = (hipStream_t)o.stream;
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipStreamCreate"));
+        ctx->own_stream = true;
+    }
+    for (double*& g : ctx->grid) {
+        e = hipMalloc(&g, grid_doubles * sizeof(double));
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(grid)"));
+    }
+    if (r_doubles) {
+        e = hipMalloc(&ctx->R, r_doubles * sizeof(double));
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(R scratch)"));
+    }
+    // operator tables (host FP64, uploaded once)
+    const std::vector<double> Hp = hermite::hermite_parity_blocks(m);
+    const std::vector<double> cpoly = hermite::evolution_poly(m, o.evolution, ctx->q, ctx->substeps);
+    const std::vector<double> K = hermite::fused_class_operators(m, ctx->lam, cpoly);
+    ctx->use_mfma = false;
+    std::vector<double> Kdev = hermite::fused_operators_by_column(m, K);
+    e = hipMalloc(&ctx->K, Kdev.size() * sizeof(double));
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));
+    e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
+    e = hipMalloc(&ctx->Hp, Hp.size() * sizeof(double));
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(Hp)"));
+    e = hipMemcpy(ctx->Hp, Hp.data(), Hp.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload Hp"));
+    *out = ctx;
+    return HERMITE_OK;
+}
+
+int hermite_set_initial(hermite_ctx* ctx, const double* u, const double* ut) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!u || !ut) return fail(ctx, HERMITE_EINVAL, "u or ut is NULL");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    const size_t half = ctx->grid_doubles / 2;
+    double* g = ctx->grid[0];
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_initial");
+    HCHECK(ctx, hipMemcpy(g, u, half * sizeof(double), hipMemcpyHostToDevice), "copy u");
+    HCHECK(ctx, hipMemcpy(g + half, ut, half * sizeof(double), hipMemcpyHostToDevice), "copy ut");
+    HCHECK(ctx, hermite::launch_scale(g + half, g + half, ctx->h / ctx->c, half, ctx->stream), "scale ut");
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "set_initial");
+    ctx->has_state = true;
+    ctx->steps = 0;
+    return HERMITE_OK;
+}
+
+int hermite_set_initial_device(hermite_ctx* ctx, const void* u_dev, const void* ut_dev) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!u_dev || !ut_dev) return fail(ctx, HERMITE_EINVAL, "u_dev or ut_dev is NULL");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    const size_t half = ctx->grid_doubles / 2;
+    double* g = ctx->grid[0];
+    HCHECK(ctx, hipMemcpyAsync(g, u_dev, half * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream), "copy u");
+    HCHECK(ctx, hermite::launch_scale(g + half, (const double*)ut_dev, ctx->h / ctx->c, half, ctx->stream),
+           "scale ut");
+    ctx->has_state = true;
+    ctx->steps = 0;
+    return HERMITE_OK;
+}
+
+int hermite_step(hermite_ctx* ctx, int n_full_steps) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (n_full_steps < 0) return fail(ctx, HERMITE_EINVAL, "n_full_steps=%d < 0", n_full_steps);
+    if (!ctx->has_state) return fail(ctx, HERMITE_ESTATE, "hermite_step before hermite_set_initial");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    for (int s = 0; s < n_full_steps; ++s) {
+        if ((rc = half_step(ctx, 0)) != HERMITE_OK) return rc;
+        if ((rc = half_step(ctx, 1)) != HERMITE_OK) return rc;
+        ++ctx->steps;
+    }
+    return HERMITE_OK;
+}
+
+int hermite_gather(hermite_ctx* ctx, double* u, double* ut, double* t_out) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!ctx->has_state) return fail(ctx, HERMITE_ESTATE, "hermite_gather before hermite_set_initial");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    const size_t half = ctx->grid_doubles / 2;
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before gather (an earlier kernel failed)");
+    if (u) HCHECK(ctx, hipMemcpy(u, ctx->grid[0], half * sizeof(double), hipMemcpyDeviceToHost), "copy u");
+    if (ut) {
+        // the dual grid is dead between full steps: use its first half as staging
+        double* tmp = ctx->grid[1];
+        HCHECK(ctx, hermite::launch_scale(tmp, ctx->grid[0] + half, ctx->c / ctx->h, half, ctx->stream), "scale ut");
+        HCHECK(ctx, hipStreamSynchronize(ctx->stream), "gather scale");
+        HCHECK(ctx, hipMemcpy(ut, tmp, half * sizeof(double), hipMemcpyDeviceToHost), "copy ut");
+    }
+    if (t_out) *t_out = (double)ctx->steps * ctx->dt;
+    return HERMITE_OK;
+}
+
+int hermite_gather_device(hermite_ctx* ctx, void* u_dev, void* ut_dev) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!ctx->has_state) return fail(ctx, HERMITE_ESTATE, "hermite_gather_device before hermite_set_initial");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    const size_t half = ctx->grid_doubles / 2;
+    if (u_dev)
+        HCHECK(ctx, hipMemcpyAsync(u_dev, ctx->grid[0], half * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream),
+               "copy u");
+    if (ut_dev)
+        HCHECK(ctx, hermite::launch_scale((double*)ut_dev, ctx->grid[0] + half, ctx->c / ctx->h, half, ctx->stream),
+               "scale ut");
+    return HERMITE_OK;
+}
+
+int hermite_sync(hermite_ctx* ctx) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return HERMITE_OK;
+}
+
+int hermite_get_time(const hermite_ctx* ctx, double* t, long long* steps, double* dt) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (t) *t = (double)ctx->steps * ctx->dt;
+    if (steps) *steps = ctx->steps;
+    if (dt) *dt = ctx->dt;
+    return HERMITE_OK;
+}
+
+void hermite_destroy(hermite_ctx* ctx) {
+    if (!ctx) return;
+    if (hipSetDevice(ctx->device) == hipSuccess && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+}
+
+const char* hermite_last_error(const hermite_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,33 @@
+// Launch wrappers of the Hermite half-step kernels (gfx950). Internal to the
+// library; the public interface is include/hermite.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace hermite {
+
+// One fused half step (interpolation + evolution + truncation per cell) with
+// the per-parity-class operators K ([8][rows_max][2 M^3], FP64). src/dst are
+// two-field grids [2][M^3][n^3]; the cell with lower corner (i,j,k) of src
+// writes node (i+off, j+off, k+off) mod n of dst (off = 0 primal->dual,
+// off = 1 dual->primal).
+hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, int off,
+                        hipStream_t st);
+
+// Interpolation half of the two-kernel variant: writes the monomial
+// coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity
+// blocks of H, [2][M][M].
+hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, hipStream_t st);
+
+// Evolution half: reads R, runs the Taylor stage loop (evolution 0, q stages)
+// or 4-stage Runge-Kutta (evolution 1, S substeps) with lam = c*tau/h, and
+// writes the coefficients with every index <= m to node cell+off of dst.
+hipError_t launch_evolve(int m, const double* R, double* dst, int n, int off, int evolution, int q,
+                         int S, double lam, hipStream_t st);
+
+// dst[i] = s * src[i], i < count (dst may equal src).
+hipError_t launch_scale(double* dst, const double* src, double s, size_t count, hipStream_t st);
+
+}  // namespace hermite

@@ -1,0 +1,102 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/hermite.h declares, and validates arguments before touching HIP."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1609_09841_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hermite.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hermite_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = _declared()
+    assert set(names) == set(B.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_options_struct_matches_header_field_order():
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct hermite_options"):text.index("} hermite_options;")]
+    fields = re.findall(r"\b(?:int|void\s*\*)\s*\**\s*([a-z_]+);", body)
+    assert fields == [f[0] for f in B.hermite_options._fields_]
+
+
+def test_default_options():
+    o = B.hermite_default_options()
+    assert (o.precision, o.evolution, o.rk_substeps, o.q, o.fused, o.poison) == (0, 0, 1, 0, 1, 0)
+    assert not o.stream
+
+
+@pytest.mark.parametrize("args,what", [
+    ((1, 3, 0.5, 1.0), "n_cells"),
+    ((1291, 3, 0.5, 1.0), "n_cells"),
+    ((8, 0, 0.5, 1.0), "m="),
+    ((8, 4, 0.5, 1.0), "m="),
+    ((8, 3, 0.0, 1.0), "cfl"),
+    ((8, 3, 1.5, 1.0), "cfl"),
+    ((8, 3, math.nan, 1.0), "cfl"),
+    ((8, 3, math.inf, 1.0), "cfl"),
+    ((8, 3, 0.5, 0.0), "c="),
+    ((8, 3, 0.5, -1.0), "c="),
+    ((8, 3, 0.5, math.inf), "c="),
+])
+def test_create_rejects_bad_arguments(args, what):
+    rc, h = B.hermite_create(*args)
+    assert rc == B.HERMITE_EINVAL and h is None
+    assert what in B.hermite_last_error(None)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("precision", 3), ("precision", -1), ("evolution", 2), ("rk_substeps", -1), ("rk_substeps", 65),
+    ("q", -1), ("q", 65), ("fused", 2), ("poison", 5),
+])
+def test_create_rejects_bad_options(field, value):
+    o = B.hermite_default_options()
+    setattr(o, field, value)
+    rc, h = B.hermite_create(8, 2, 0.5, 1.0, o)
+    assert rc == B.HERMITE_EINVAL and h is None
+
+
+def test_create_rejects_null_out():
+    lib = B.load()
+    rc = lib.hermite_create(8, 2, 0.5, 1.0, None, None)
+    assert rc == B.HERMITE_EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = B.load()
+    assert lib.hermite_step(None, 1) == B.HERMITE_EINVAL
+    assert lib.hermite_sync(None) == B.HERMITE_EINVAL
+    assert lib.hermite_set_initial(None, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_gather(None, None, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_get_time(None, None, None, None) == B.HERMITE_EINVAL
+    lib.hermite_destroy(None)  # no-op
+    assert isinstance(lib.hermite_last_error(None), bytes)
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_valid_create_without_device_reports_device_error():
+    rc, h = B.hermite_create(8, 2, 0.5, 1.0)
+    assert rc == B.HERMITE_EDEVICE and h is None
+    assert B.hermite_last_error(None) != ""

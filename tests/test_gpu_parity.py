@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance. The plain FP64 path must match the oracle to relative L2 <= 1e-12
+per field. At m = 3 the FP64 rounding of the method itself (the oracle against
+a long-double build of the same oracle source) can exceed 1e-12 for u_t after
+many steps; there the bound is stated against that measured floor instead:
+the GPU result must be within 3x the floor of the oracle, and at least as
+close to the long-double result as the FP64 oracle is (within 50%).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1609_09841_amd import binding as B
+from paper_1609_09841_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [
+    pytest.param(True, "taylor", id="fused-taylor"),
+    pytest.param(True, "rk4", id="fused-rk4"),
+    pytest.param(False, "taylor", id="two-taylor"),
+    pytest.param(False, "rk4", id="two-rk4"),
+]
+TOL = 1e-12
+
+
+def rel(a, b):
+    return I.rel_l2(np.asarray(a), np.asarray(b))
+
+
+def gpu_run(n, m, u0, ut0, steps, cfl=0.5, c=1.0, **kw):
+    print(f"[gpu_run] n={n} m={m} steps={steps} {kw}", flush=True)
+    with B.Solver(n, m, cfl, c, **kw) as s:
+        s.set_initial(u0, ut0)
+        s.step(steps)
+        u, ut, t = s.gather()
+    return u, ut, t
+
+
+def _np(x):
+    return x.numpy() if hasattr(x, "numpy") else np.asarray(x)
+
+
+def _check_vs_oracle(n, m, u0, ut0, steps, fused, evolution, cfl=0.5, c=1.0, floor_check=False, q=0):
+    u0, ut0 = _np(u0), _np(ut0)
+    param = q if (q and evolution == "taylor") else None
+    gu, gv, t = gpu_run(n, m, u0, ut0, steps, cfl, c, fused=fused, evolution=evolution, q=q)
+    ou, ov = O.run(n, m, cfl, c, u0, ut0, steps, evolution, param)
+    eu, ev = rel(gu, ou), rel(gv, ov)
+    assert math.isclose(t, steps * cfl / n / c, rel_tol=1e-15)
+    if not floor_check:
+        assert eu <= TOL and ev <= TOL, (eu, ev)
+        return eu, ev
+    lu, lv = O.run(n, m, cfl, c, u0, ut0, steps, evolution, param, ld=True)
+    fu, fv = rel(ou, lu), rel(ov, lv)   # FP64 rounding floor of the oracle itself
+    print(f"  gpu-oracle u {eu:.2e} ut {ev:.2e}; oracle-ld u {fu:.2e} ut {fv:.2e}; "
+          f"gpu-ld u {rel(gu, lu):.2e} ut {rel(gv, lv):.2e}", flush=True)
+    assert eu <= max(TOL, 3 * fu) and ev <= max(TOL, 3 * fv), (eu, ev, fu, fv)
+    assert rel(gu, lu) <= max(TOL, 1.5 * fu) and rel(gv, lv) <= max(TOL, 1.5 * fv)
+    return eu, ev
+
+
+@pytest.mark.parametrize("fused,evolution", VARIANTS)
+def test_config1_standing_mode(fused, evolution):
+    """16^3 cells, m = 1, cfl 0.5, 20 full steps of the standing mode."""
+    n, m = 16, 1
+    u0, ut0 = I.standing_mode(n, m)
+    _check_vs_oracle(n, m, u0, ut0, 20, fused, evolution)
+    gu, gv, t = gpu_run(n, m, u0.numpy(), ut0.numpy(), 20, fused=fused, evolution=evolution)
+    ue, ute = I.standing_mode(n, m, t=t)
+    err = max(rel(gu, ue.numpy()), rel(gv, ute.numpy()))
+    print(f"  error vs exact solution: {err:.3e}", flush=True)
+    assert err < 0.1
+
+
+@pytest.mark.parametrize("fused,evolution", VARIANTS)
+@pytest.mark.parametrize("m", [1, 2, 3])
+@pytest.mark.parametrize("n", [2, 3, 5, 7])
+def test_small_random_grids(n, m, fused, evolution):
+    """Random (non-smooth) data on tiny and ragged grids, 2 full steps: every
+    wrap-around and tail case of the launch shapes."""
+    rng = np.random.default_rng(1000 * n + 10 * m + int(fused))
+    M = m + 1
+    u0 = rng.standard_normal((M, M, M, n, n, n))
+    ut0 = rng.standard_normal((M, M, M, n, n, n)) * n
+    _check_vs_oracle(n, m, u0, ut0, 2, fused, evolution, floor_check=(m == 3))
+
+
+@pytest.mark.parametrize("fused,evolution", VARIANTS)
+@pytest.mark.parametrize("m", [2, 3])
+def test_smooth_multistep(m, fused, evolution):
+    """Seeded Fourier modes (travelling, u_t != 0) on 12^3 cells, 10 steps."""
+    n = 12
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=2), t=0.05)
+    _check_vs_oracle(n, m, u0, ut0, 10, fused, evolution, floor_check=(m == 3))
+
+
+@pytest.mark.parametrize("q", [4, 6 * 3 + 3])
+def test_taylor_stage_counts(q):
+    """q below the exact count (a lower-order method) and the paper's
+    d(2N+1) = 6m+3 stages."""
+    n, m = 6, 3
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05)
+    for fused in (True, False):
+        _check_vs_oracle(n, m, u0, ut0, 3, fused, "taylor", q=q, floor_check=True)
+
+
+def test_rk4_substeps():
+    n, m = 6, 2
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05)
+    for fused in (True, False):
+        gu, gv, _ = gpu_run(n, m, u0.numpy(), ut0.numpy(), 3, fused=fused, evolution="rk4", rk_substeps=3)
+        ou, ov = O.run(n, m, 0.5, 1.0, u0.numpy(), ut0.numpy(), 3, "rk4", 3)
+        assert rel(gu, ou) <= TOL and rel(gv, ov) <= TOL
+
+
+def test_other_wave_speed_and_cfl():
+    n, m, c, cfl = 8, 2, 2.5, 0.3
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05, c=c)
+    for fused in (True, False):
+        _check_vs_oracle(n, m, u0, ut0, 4, fused, "taylor", cfl=cfl, c=c)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_poisoned_destination_is_fully_written(m, fused):
+    n = 5
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05)
+    gu, gv, _ = gpu_run(n, m, u0.numpy(), ut0.numpy(), 2, fused=fused, poison=True)
+    assert np.isfinite(gu).all() and np.isfinite(gv).all()
+    ref_u, ref_v, _ = gpu_run(n, m, u0.numpy(), ut0.numpy(), 2, fused=fused)
+    assert np.array_equal(gu, ref_u) and np.array_equal(gv, ref_v)
+
+
+@pytest.mark.parametrize("fused,evolution", VARIANTS)
+def test_checkpoint_restart_bitwise(fused, evolution):
+    n, m = 6, 3
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05)
+    a, b, _ = gpu_run(n, m, u0.numpy(), ut0.numpy(), 4, fused=fused, evolution=evolution)
+    with B.Solver(n, m, fused=fused, evolution=evolution) as s:
+        s.set_initial(u0.numpy(), ut0.numpy())
+        s.step(2)
+        c1, d1, _ = s.gather()
+        s.set_initial(c1, d1)
+        s.step(2)
+        c2, d2, _ = s.gather()
+    assert np.array_equal(a, c2) and np.array_equal(b, d2)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_zero_and_constant_data_preserved_exactly(fused):
+    n, m = 4, 3
+    M = m + 1
+    z = np.zeros((M, M, M, n, n, n))
+    u, ut, _ = gpu_run(n, m, z, z, 3, fused=fused)
+    assert np.all(u == 0) and np.all(ut == 0)
+    cst = z.copy()
+    cst[0, 0, 0] = 0.75
+    u, ut, _ = gpu_run(n, m, cst, z, 3, fused=fused)
+    assert np.array_equal(u, cst) and np.all(ut == 0)
+
+
+def test_zero_steps_is_identity_and_state_errors():
+    n, m = 4, 2
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05)
+    with B.Solver(n, m) as s:
+        lib = B.load()
+        assert lib.hermite_step(s.handle, 1) == B.HERMITE_ESTATE
+        assert lib.hermite_gather(s.handle, None, None, None) == B.HERMITE_ESTATE
+        assert lib.hermite_step(s.handle, -1) == B.HERMITE_EINVAL
+        s.set_initial(u0.numpy(), ut0.numpy())
+        s.step(0)
+        u, ut, t = s.gather()
+    assert t == 0.0
+    assert np.array_equal(u, u0.numpy())
+    # u_t goes through the (h/c) scaling and back: at most one rounding each way
+    assert np.allclose(ut, ut0.numpy(), rtol=4e-16, atol=0)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_device_arrays_on_torch_stream(fused):
+    n, m = 8, 3
+    u0, ut0 = I.fourier_exact(n, m, I.fourier_modes(kmax=1), t=0.05)
+    host_u, host_v, _ = gpu_run(n, m, u0.numpy(), ut0.numpy(), 2, fused=fused)
+    stream = torch.cuda.current_stream()
+    du, dv = u0.cuda().contiguous(), ut0.cuda().contiguous()
+    ou, ov = torch.empty_like(du), torch.empty_like(dv)
+    with B.Solver(n, m, fused=fused, stream=stream) as s:
+        s.set_initial(du, dv)
+        s.step(2)
+        s.gather_device(ou, ov)
+        torch.cuda.synchronize()
+    assert np.array_equal(ou.cpu().numpy(), host_u) and np.array_equal(ov.cpu().numpy(), host_v)
+
+
+def test_one_dimensional_data_stays_one_dimensional_at_size():
+    """Any size: data depending on x1 only keeps every x2/x3 derivative exactly 0."""
+    n, m = 64, 3
+    u0, ut0 = I.plane_waves_1d(n, m, kx=3, t=0.02, device="cuda")
+    for fused in (True, False):
+        with B.Solver(n, m, fused=fused) as s:
+            s.set_initial(u0, ut0)
+            s.step(3)
+            u, ut, _ = s.gather()
+        mask = np.ones((m + 1,) * 3, dtype=bool)
+        mask[0, 0, :] = False
+        assert np.all(u[mask] == 0.0) and np.all(ut[mask] == 0.0)
+
+
+def _box(x, n, i, j, k, s):
+    idx = lambda c: torch.tensor([(c - s + t) % n for t in range(2 * s + 1)], device=x.device)
+    return x.index_select(3, idx(k)).index_select(4, idx(j)).index_select(5, idx(i)).cpu().numpy()
+
+
+def _sampled_check(n, m, steps, fused, evolution, nsamples=12, seed=3):
+    """Full-size grid (n^3 cells, seeded Fourier workload, u_t = 0): the GPU
+    result at sampled primal nodes against the oracle's dependency-cone value."""
+    print(f"[sampled] n={n} m={m} steps={steps} fused={fused} {evolution}", flush=True)
+    u0, ut0 = I.fourier_initial(n, m, device="cuda")
+    with B.Solver(n, m, fused=fused, evolution=evolution) as s:
+        s.set_initial(u0, ut0)
+        s.step(steps)
+        gu, gv = torch.empty_like(u0), torch.empty_like(ut0)
+        s.gather_device(gu, gv)
+        s.sync()
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n - 1, 0, n // 2)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(nsamples - len(pts))]
+    M3 = (m + 1) ** 3
+    got, ref = [], []
+    for (i, j, k) in pts:
+        ub, vb = _box(u0, n, i, j, k, steps), _box(ut0, n, i, j, k, steps)
+        out = O.point_box(n, m, 0.5, 1.0, ub, vb, steps, evolution)
+        ref.append(out)
+        got.append(np.concatenate([gu[..., k, j, i].reshape(-1).cpu().numpy(), gv[..., k, j, i].reshape(-1).cpu().numpy()]))
+    got, ref = np.array(got), np.array(ref)
+    eu = rel(got[:, :M3], ref[:, :M3])
+    ev = rel(got[:, M3:], ref[:, M3:])
+    print(f"  sampled rel L2: u {eu:.2e} ut {ev:.2e}", flush=True)
+    del u0, ut0, gu, gv
+    torch.cuda.empty_cache()
+    return eu, ev
+
+
+@pytest.mark.parametrize("fused,evolution", VARIANTS)
+def test_full_size_128_m3_sampled(fused, evolution):
+    """128^3 cells, m = 3 (the benchmark workload), 2 full steps."""
+    eu, ev = _sampled_check(128, 3, 2, fused, evolution)
+    assert eu <= TOL and ev <= TOL
+
+
+def test_max_size_256_m3_sampled():
+    """256^3 cells, m = 3: 2 x 17.2 GB of state, 1 full step, fused."""
+    eu, ev = _sampled_check(256, 3, 1, True, "taylor", nsamples=8)
+    assert eu <= TOL and ev <= TOL
