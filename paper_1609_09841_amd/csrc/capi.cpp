@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -26,7 +27,8 @@ struct hermite_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    bool use_mfma = false;
+    int cus = 0;             // compute units of the device (persistent grids)
+    bool use_mfma = false;   // m = 3 fused FP64 on the matrix cores
     double* grid[2] = {nullptr, nullptr};  // primal, dual: [2][M^3][n^3] each
     double* R = nullptr;                   // two-kernel scratch [2][P^3][n^3]
     double* K = nullptr;                   // fused class operators
@@ -85,7 +87,12 @@ int half_step(hermite_ctx* ctx, int from) {
         HCHECK(ctx, hipMemsetAsync(dst, 0xFF, ctx->grid_doubles * sizeof(double), ctx->stream), "poison");
     hipError_t e;
     if (ctx->opt.fused) {
-        e = hermite::launch_fused(ctx->m, src, dst, ctx->K, ctx->n, off, ctx->stream);
+        if (ctx->use_mfma) {
+            const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
+            e = hermite::launch_fused_mfma(src, dst, ctx->K, ctx->n, off, grid, ctx->stream);
+        } else {
+            e = hermite::launch_fused(ctx->m, src, dst, ctx->K, ctx->n, off, ctx->stream);
+        }
         if (e != hipSuccess) return hip_fail(ctx, e, "fused half-step launch");
     } else {
         e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->stream);
@@ -183,8 +190,19 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     const std::vector<double> Hp = hermite::hermite_parity_blocks(m);
     const std::vector<double> cpoly = hermite::evolution_poly(m, o.evolution, ctx->q, ctx->substeps);
     const std::vector<double> K = hermite::fused_class_operators(m, ctx->lam, cpoly);
-    ctx->use_mfma = false;
-    std::vector<double> Kdev = hermite::fused_operators_by_column(m, K);
+    e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipDeviceGetAttribute"));
+    // The m = 3 fused FP64 half step runs on the matrix cores unless
+    // HERMITE_FUSED_KERNEL=valu asks for the vector kernel (comparison runs).
+    const char* kern = std::getenv("HERMITE_FUSED_KERNEL");
+    ctx->use_mfma = (m == 3) && o.fused && !(kern && std::strcmp(kern, "valu") == 0);
+    std::vector<double> Kdev;
+    if (ctx->use_mfma) {
+        Kdev.resize(hermite::mfma_operator_doubles());
+        hermite::mfma_permute_operators(K.data(), Kdev.data());
+    } else {
+        Kdev = hermite::fused_operators_by_column(m, K);
+    }
     e = hipMalloc(&ctx->K, Kdev.size() * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));
     e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size() * sizeof(double), hipMemcpyHostToDevice);

@@ -16,6 +16,14 @@ namespace hermite {
 hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, int off,
                         hipStream_t st);
 
+// Same fused half step on the FP64 matrix cores (m = 3 only). Kperm: the
+// class operators permuted by mfma_permute_operators (mfma_operator_doubles()
+// doubles). grid: workgroups, a multiple of 8 (one per CU is enough).
+hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, int off, int grid,
+                             hipStream_t st);
+void mfma_permute_operators(const double* K, double* Kperm);
+size_t mfma_operator_doubles();
+
 // Interpolation half of the two-kernel variant: writes the monomial
 // coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity
 // blocks of H, [2][M][M].
