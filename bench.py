@@ -64,8 +64,12 @@ def variant_kwargs(v: str) -> dict:
 
 
 def time_variant(B, torch, n, m, u0, ut0, steps, warmup, variant):
-    stream = torch.cuda.current_stream()
-    with B.Solver(n, m, 0.5, 1.0, stream=stream, **variant_kwargs(variant)) as s:
+    # A stream of our own (default priority): torch's current stream is the
+    # null stream, which the library would replace by a private one, and the
+    # timing events must sit on the stream the kernels run on.
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream), B.Solver(n, m, 0.5, 1.0, stream=stream, **variant_kwargs(variant)) as s:
         s.set_initial(u0, ut0)
         s.step(warmup)
         s.sync()
@@ -137,9 +141,11 @@ def main():
     if args.variant.startswith("fused"):
         flops = fused_flops_per_cell(m) * cells
         achieved_tflops = flops / avg_launch_s / 1e12
-        roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_VALU_PEAK_TFLOPS,
+        mfma = (m == 3)
+        roofline = {"bound": "mfma" if mfma else "alu", "achieved": achieved_tflops,
+                    "peak": FP64_MFMA_PEAK_TFLOPS if mfma else FP64_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-                    "kernel": f"fused_kernel<{m + 1}> (FP64 VALU)",
+                    "kernel": "fused_mfma_kernel (FP64 MFMA 16x16x4)" if mfma else f"fused_kernel<{m + 1}> (FP64 VALU)",
                     "avg_launch_ms": avg_launch_s * 1e3,
                     "hbm_GBps_algorithmic": fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9}
     else:

@@ -242,18 +242,20 @@ def point(n: int, m: int, cfl: float, c: float, u: np.ndarray, ut: np.ndarray, n
 
 
 def point_box(n: int, m: int, cfl: float, c: float, ubox: np.ndarray, utbox: np.ndarray, nsteps: int,
-              evolution: str = "taylor", param: int | None = None):
+              evolution: str = "taylor", param: int | None = None, ld: bool = False):
     """Values (u then u_t) at the centre primal node of a (2*nsteps+1)^3 box of
     primal nodes, laid out [M^3][w][w][w], after nsteps full steps (grid of n
-    cells per side, so h = 1/n)."""
+    cells per side, so h = 1/n). ld=True runs the long-double twin (rounding
+    floor measurements only)."""
     evo, param = _evo(m, evolution, param)
-    a = np.ascontiguousarray(np.asarray(ubox, dtype=np.float64).ravel())
-    b = np.ascontiguousarray(np.asarray(utbox, dtype=np.float64).ravel())
+    dt = np.longdouble if ld else np.float64
+    a = np.ascontiguousarray(np.asarray(ubox, dtype=np.float64).astype(dt).ravel())
+    b = np.ascontiguousarray(np.asarray(utbox, dtype=np.float64).astype(dt).ravel())
     w = 2 * nsteps + 1
     assert a.size == (m + 1) ** 3 * w ** 3 and b.size == a.size
-    out = np.zeros(2 * (m + 1) ** 3)
-    rc = load().oracle_point_box(n, m, float(cfl), float(c), evo, param, int(nsteps),
-                                 _ptr(a), _ptr(b), _ptr(out))
+    out = np.zeros(2 * (m + 1) ** 3, dtype=dt)
+    rc = load(ld).oracle_point_box(n, m, float(cfl), float(c), evo, param, int(nsteps),
+                                   _ptr(a), _ptr(b), _ptr(out))
     if rc != 0:
         raise ValueError(f"oracle_point_box failed: {rc}")
-    return out
+    return out.astype(np.float64)

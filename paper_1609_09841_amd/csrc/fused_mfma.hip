@@ -7,7 +7,11 @@
 // 16 x 128 x 16 product per class, i.e. 32 v_mfma_f64_16x16x4f64 steps:
 //   A (16 x 4): the class operator, rows = outputs, 4 input columns per step,
 //   B (4 x 16): the class inputs of those 4 columns for the 16 cells,
-//   D (16 x 16): accumulated outputs, lane l holds rows 4(l/16)..+3 of cell l%16.
+//   D (16 x 16): accumulated outputs; register r of lane l holds row
+//      4r + l/16 of column (cell) l%16 (the FP64 16x16x4 output layout).
+// The operator rows are stored permuted (row 4r + g of A holds logical row
+// 4g + r) so that register r of lane quarter g ends up with logical output
+// row 4g + r: the quarter g = (field, o3) and r = (o2, o1).
 // Lane l = (quarter q = l/16, cell l%16) loads the 8 corners of input column
 // q of the current step for its cell and forms all 8 butterfly outputs, one
 // per class. The 4 columns of a step share the parity pattern of d, so the
@@ -146,8 +150,8 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* _
         load_step<0>(src, plane, c, q, v);
         Steps<0>::run(src, plane, c, q, lane, sK, acc, v);
         if (!valid) continue;
-        // D row 4q + r of class p: output field q/2, derivative orders
-        // j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2
+        // logical output row 4q + r of class p (register r of quarter q): field q/2,
+        // derivative orders j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2
         const int fo = q >> 1, o3 = q & 1;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
@@ -168,12 +172,18 @@ size_t mfma_operator_doubles() { return (size_t)kOpDoubles; }
 
 void mfma_permute_operators(const double* K, double* Kperm) {
     // K: [8][16][128] canonical class operators (rows (fo, o3, o2, o1), columns
-    // f*64 + dd); Kperm[p][t][lane] = K[p][lane % 16][col(t, lane / 16)]
+    // f*64 + dd). A operand of step t: lane l holds A[l % 16][l / 16]. The
+    // MFMA leaves output row i in register i / 4 of lane quarter i % 4, so A
+    // row i carries logical row 4 (i % 4) + i / 4: register r of quarter g then
+    // holds logical row 4g + r.
+    //   Kperm[p][t][lane] = K[p][4 (i % 4) + i / 4][col(t, lane / 16)], i = lane % 16
     constexpr MfmaSchedule S{};
     for (int p = 0; p < 8; ++p)
         for (int t = 0; t < 32; ++t)
-            for (int lane = 0; lane < 64; ++lane)
-                Kperm[((size_t)p * 32 + t) * 64 + lane] = K[((size_t)p * 16 + (lane & 15)) * 128 + S.col[t][lane >> 4]];
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = lane & 15, row = 4 * (i & 3) + (i >> 2);
+                Kperm[((size_t)p * 32 + t) * 64 + lane] = K[((size_t)p * 16 + row) * 128 + S.col[t][lane >> 4]];
+            }
 }
 
 hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, int off, int grid,
