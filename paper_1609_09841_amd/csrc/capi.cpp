@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hermite.h"
+#include "hermite.h"
 #include "constants.h"
 #include "kernels.h"
 
@@ -29,8 +29,10 @@ struct hermite_ctx {
     int device = 0;
     int cus = 0;             // compute units of the device (persistent grids)
     bool use_mfma = false;   // m = 3 fused FP64 on the matrix cores
-    double* grid[2] = {nullptr, nullptr};  // primal, dual: [2][M^3][n^3] each
-    double* R = nullptr;                   // two-kernel scratch [2][P^3][n^3]
+    double* grid[2] = {nullptr, nullptr};  // primal, dual: 2 M^3 columns of `pitch` doubles each
+    double* R = nullptr;                   // two-kernel scratch: 2 P^3 columns of `pitch` doubles
+    size_t ncell = 0;                      // n^3 nodes per column
+    size_t pitch = 0;                      // doubles between consecutive columns (>= ncell)
     double* K = nullptr;                   // fused class operators
     double* Hp = nullptr;                  // parity blocks of H
     size_t grid_doubles = 0;
@@ -74,6 +76,13 @@ void free_all(hermite_ctx* ctx) {
     if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
 }
 
+// Column pitch of the device grids: n^3 rounded up to whole 256-byte blocks,
+// plus 5 cache lines (640 bytes). With the unpadded power-of-two strides of
+// the common grid sizes, the 2 M^3 columns of one node (and of its
+// neighbours) all map to the same L2 set and channel, and the cache holds
+// almost none of the data that the 8 cells around a node share.
+size_t column_pitch(size_t ncell) { return ((ncell + 31) / 32) * 32 + 80; }
+
 int select_device(hermite_ctx* ctx) {
     HCHECK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     return HERMITE_OK;
@@ -89,16 +98,16 @@ int half_step(hermite_ctx* ctx, int from) {
     if (ctx->opt.fused) {
         if (ctx->use_mfma) {
             const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
-            e = hermite::launch_fused_mfma(src, dst, ctx->K, ctx->n, off, grid, ctx->stream);
+            e = hermite::launch_fused_mfma(src, dst, ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
         } else {
-            e = hermite::launch_fused(ctx->m, src, dst, ctx->K, ctx->n, off, ctx->stream);
+            e = hermite::launch_fused(ctx->m, src, dst, ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "fused half-step launch");
     } else {
-        e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->stream);
+        e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->pitch, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "interpolation launch");
-        e = hermite::launch_evolve(ctx->m, ctx->R, dst, ctx->n, off, ctx->opt.evolution, ctx->q, ctx->substeps,
-                                   ctx->lam, ctx->stream);
+        e = hermite::launch_evolve(ctx->m, ctx->R, dst, ctx->n, ctx->pitch, off, ctx->opt.evolution, ctx->q,
+                                   ctx->substeps, ctx->lam, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "evolution launch");
     }
     return HERMITE_OK;
@@ -142,8 +151,9 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
 
     const int M = m + 1, P = 2 * m + 2;
     const size_t nn = (size_t)n_cells * n_cells * n_cells;
-    const size_t grid_doubles = (size_t)2 * M * M * M * nn;
-    const size_t r_doubles = o.fused ? 0 : (size_t)2 * P * P * P * nn;
+    const size_t pitch = column_pitch(nn);
+    const size_t grid_doubles = (size_t)2 * M * M * M * pitch;
+    const size_t r_doubles = o.fused ? 0 : (size_t)2 * P * P * P * pitch;
 
     hermite_ctx* ctx = new (std::nothrow) hermite_ctx();
     if (!ctx) return fail(nullptr, HERMITE_ENOMEM, "host allocation failed");
@@ -160,6 +170,8 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     ctx->q = o.q ? o.q : 6 * m + 1;
     ctx->substeps = o.rk_substeps ? o.rk_substeps : 1;
     ctx->grid_doubles = grid_doubles;
+    ctx->ncell = nn;
+    ctx->pitch = pitch;
 
     auto bail = [&](int code) {
         g_err = ctx->err;
@@ -220,12 +232,14 @@ int hermite_set_initial(hermite_ctx* ctx, const double* u, const double* ut) {
     if (!u || !ut) return fail(ctx, HERMITE_EINVAL, "u or ut is NULL");
     int rc = select_device(ctx);
     if (rc) return rc;
-    const size_t half = ctx->grid_doubles / 2;
+    const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), dp = ctx->pitch * sizeof(double);
     double* g = ctx->grid[0];
+    double* gv = g + rows * ctx->pitch;
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_initial");
-    HCHECK(ctx, hipMemcpy(g, u, half * sizeof(double), hipMemcpyHostToDevice), "copy u");
-    HCHECK(ctx, hipMemcpy(g + half, ut, half * sizeof(double), hipMemcpyHostToDevice), "copy ut");
-    HCHECK(ctx, hermite::launch_scale(g + half, g + half, ctx->h / ctx->c, half, ctx->stream), "scale ut");
+    HCHECK(ctx, hipMemcpy2D(g, dp, u, w, w, rows, hipMemcpyHostToDevice), "copy u");
+    HCHECK(ctx, hipMemcpy2D(gv, dp, ut, w, w, rows, hipMemcpyHostToDevice), "copy ut");
+    HCHECK(ctx, hermite::launch_scale(gv, ctx->pitch, gv, ctx->pitch, ctx->h / ctx->c, ctx->ncell, ctx->M3, ctx->stream),
+           "scale ut");
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "set_initial");
     ctx->has_state = true;
     ctx->steps = 0;
@@ -237,10 +251,12 @@ int hermite_set_initial_device(hermite_ctx* ctx, const void* u_dev, const void* 
     if (!u_dev || !ut_dev) return fail(ctx, HERMITE_EINVAL, "u_dev or ut_dev is NULL");
     int rc = select_device(ctx);
     if (rc) return rc;
-    const size_t half = ctx->grid_doubles / 2;
+    const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), dp = ctx->pitch * sizeof(double);
     double* g = ctx->grid[0];
-    HCHECK(ctx, hipMemcpyAsync(g, u_dev, half * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream), "copy u");
-    HCHECK(ctx, hermite::launch_scale(g + half, (const double*)ut_dev, ctx->h / ctx->c, half, ctx->stream),
+    double* gv = g + rows * ctx->pitch;
+    HCHECK(ctx, hipMemcpy2DAsync(g, dp, u_dev, w, w, rows, hipMemcpyDeviceToDevice, ctx->stream), "copy u");
+    HCHECK(ctx, hermite::launch_scale(gv, ctx->pitch, (const double*)ut_dev, ctx->ncell, ctx->h / ctx->c, ctx->ncell,
+                                      ctx->M3, ctx->stream),
            "scale ut");
     ctx->has_state = true;
     ctx->steps = 0;
@@ -266,15 +282,19 @@ int hermite_gather(hermite_ctx* ctx, double* u, double* ut, double* t_out) {
     if (!ctx->has_state) return fail(ctx, HERMITE_ESTATE, "hermite_gather before hermite_set_initial");
     int rc = select_device(ctx);
     if (rc) return rc;
-    const size_t half = ctx->grid_doubles / 2;
+    const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), sp = ctx->pitch * sizeof(double);
+    const double* g = ctx->grid[0];
+    const double* gv = g + rows * ctx->pitch;
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before gather (an earlier kernel failed)");
-    if (u) HCHECK(ctx, hipMemcpy(u, ctx->grid[0], half * sizeof(double), hipMemcpyDeviceToHost), "copy u");
+    if (u) HCHECK(ctx, hipMemcpy2D(u, w, g, sp, w, rows, hipMemcpyDeviceToHost), "copy u");
     if (ut) {
-        // the dual grid is dead between full steps: use its first half as staging
+        // the dual grid is dead between full steps: use it as staging
         double* tmp = ctx->grid[1];
-        HCHECK(ctx, hermite::launch_scale(tmp, ctx->grid[0] + half, ctx->c / ctx->h, half, ctx->stream), "scale ut");
+        HCHECK(ctx, hermite::launch_scale(tmp, ctx->pitch, gv, ctx->pitch, ctx->c / ctx->h, ctx->ncell, ctx->M3,
+                                          ctx->stream),
+               "scale ut");
         HCHECK(ctx, hipStreamSynchronize(ctx->stream), "gather scale");
-        HCHECK(ctx, hipMemcpy(ut, tmp, half * sizeof(double), hipMemcpyDeviceToHost), "copy ut");
+        HCHECK(ctx, hipMemcpy2D(ut, w, tmp, sp, w, rows, hipMemcpyDeviceToHost), "copy ut");
     }
     if (t_out) *t_out = (double)ctx->steps * ctx->dt;
     return HERMITE_OK;
@@ -285,12 +305,13 @@ int hermite_gather_device(hermite_ctx* ctx, void* u_dev, void* ut_dev) {
     if (!ctx->has_state) return fail(ctx, HERMITE_ESTATE, "hermite_gather_device before hermite_set_initial");
     int rc = select_device(ctx);
     if (rc) return rc;
-    const size_t half = ctx->grid_doubles / 2;
-    if (u_dev)
-        HCHECK(ctx, hipMemcpyAsync(u_dev, ctx->grid[0], half * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream),
-               "copy u");
+    const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), sp = ctx->pitch * sizeof(double);
+    const double* g = ctx->grid[0];
+    const double* gv = g + rows * ctx->pitch;
+    if (u_dev) HCHECK(ctx, hipMemcpy2DAsync(u_dev, w, g, sp, w, rows, hipMemcpyDeviceToDevice, ctx->stream), "copy u");
     if (ut_dev)
-        HCHECK(ctx, hermite::launch_scale((double*)ut_dev, ctx->grid[0] + half, ctx->c / ctx->h, half, ctx->stream),
+        HCHECK(ctx, hermite::launch_scale((double*)ut_dev, ctx->ncell, gv, ctx->pitch, ctx->c / ctx->h, ctx->ncell,
+                                          ctx->M3, ctx->stream),
                "scale ut");
     return HERMITE_OK;
 }

@@ -78,91 +78,142 @@ __device__ __forceinline__ void butterfly8(const double* v, double* T) {
     }
 }
 
+// Input column of step T for this lane, from the lane's packed column table
+// (four 7-bit column numbers per word, filled once per kernel): branch-free,
+// so the whole step chain stays one basic block and the loads stay where the
+// pipeline puts them.
 template <int T>
-__device__ __forceinline__ void load_step(const double* __restrict__ src, size_t plane, const Cell16& c, int q,
-                                          double* v) {
-    constexpr MfmaSchedule S{};
-    constexpr int c0 = S.col[T][0], c1 = S.col[T][1], c2 = S.col[T][2], c3 = S.col[T][3];
-    const int col = (q == 0) ? c0 : (q == 1) ? c1 : (q == 2) ? c2 : c3;
-    const double* __restrict__ b = src + (size_t)col * plane;
+__device__ __forceinline__ uint32_t step_col(const uint32_t* packed) {
+    return (packed[T >> 2] >> (8 * (T & 3))) & 0xFFu;
+}
+
+template <int T>
+__device__ __forceinline__ void load_step(const double* __restrict__ src, size_t plane, const Cell16& c,
+                                          const uint32_t* packed, double* v) {
+    const double* __restrict__ b = src + (size_t)step_col<T>(packed) * plane;
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = b[c.corner[s]];
 }
 
-// One K-step: the corner values of this step (v) were loaded one step ahead;
-// the loads of the next step are issued before this step's MFMAs so that
-// their latency hides behind the matrix work. The scheduling barrier keeps
-// the compiler from hoisting every step's loads (which would spill).
+// Software pipeline depth: the corner values of step T + kAhead are requested
+// while step T runs its butterfly and matrix work.
+constexpr int kAhead = 2;
+constexpr int kRing = kAhead + 1;
+
+// One K-step. ring[T % kRing] holds this step's corner values (loaded kAhead
+// steps earlier). The scheduling barrier keeps the compiler from hoisting
+// every step's loads to the top (which would spill).
 template <int T>
 struct Steps {
-    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& c, int q,
-                                               int lane, const double* sK, d4* acc, double* v) {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& c,
+                                               const uint32_t* packed, int lane, const double* sK, d4* acc,
+                                               double (*ring)[8]) {
         constexpr MfmaSchedule S{};
         constexpr int dp = S.dpar[T];
-        double vn[8];
-        if constexpr (T + 1 < 32) load_step<T + 1>(src, plane, c, q, vn);
+        if constexpr (T + kAhead < 32) load_step<T + kAhead>(src, plane, c, packed, ring[(T + kAhead) % kRing]);
         double Tv[8];
-        butterfly8(v, Tv);
+        butterfly8(ring[T % kRing], Tv);
+        double a[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) a[p] = sK[(p * 32 + T) * 64 + lane];
         // class p takes the butterfly output t = p xor (d mod 2): a sum along
         // x when p_x and d_x agree, a difference otherwise
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const double a = sK[(p * 32 + T) * 64 + lane];
-            acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Tv[p ^ dp], acc[p], 0, 0, 0);
-        }
+        for (int p = 0; p < 8; ++p) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], Tv[p ^ dp], acc[p], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (T + 1 < 32) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) v[s] = vn[s];
-            Steps<T + 1>::run(src, plane, c, q, lane, sK, acc, v);
-        }
+        if constexpr (T + 1 < 32) Steps<T + 1>::run(src, plane, c, packed, lane, sK, acc, ring);
     }
 };
 
-// Persistent: gridDim.x is a multiple of 8 (one workgroup per CU). Workgroup
-// b runs on XCD b % 8; logical block (b % 8) * (G/8) + b/8 gives each XCD one
-// contiguous range of the domain, so node rows shared by neighbouring cells
-// meet in that XCD's L2.
+// The first kAhead steps' corner values, before the step chain starts.
+template <int T>
+struct Prologue {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& c,
+                                               const uint32_t* packed, double (*ring)[8]) {
+        load_step<T>(src, plane, c, packed, ring[T]);
+        if constexpr (T + 1 < kAhead) Prologue<T + 1>::run(src, plane, c, packed, ring);
+    }
+};
+
+// Column tables: kColTable[q][w] packs the input columns of steps 4w..4w+3
+// for lane quarter q.
+struct ColTable {
+    uint32_t w[4][8];
+    constexpr ColTable() : w() {
+        constexpr MfmaSchedule S{};
+        for (int q = 0; q < 4; ++q)
+            for (int t = 0; t < 32; ++t) w[q][t >> 2] |= (uint32_t)S.col[t][q] << (8 * (t & 3));
+    }
+};
+__constant__ ColTable kColTable = ColTable();
+
+// One batch: 16 neighbouring cells of one x-row (cells x0 .. x0+15 of row
+// (y, z); lanes past the end of the row compute a copy of the last cell and
+// store nothing).
+__device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t plane,
+                                          uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
+                                          int cl, int q, uint32_t* packed, const double* sK) {
+    const uint32_t x = x0 + cl;
+    const bool valid = x < n;
+    const Cell16 c = cell_nodes((z * n + y) * n + (valid ? x : n - 1), n, off);
+    // Opaque per batch: without this the 32 per-lane column base addresses
+    // are hoisted out of the batch loop and pin 64 registers.
+#pragma unroll
+    for (int w = 0; w < 8; ++w) asm volatile("" : "+v"(packed[w]));
+    d4 acc[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
+    double ring[kRing][8];
+    Prologue<0>::run(src, plane, c, packed, ring);
+    Steps<0>::run(src, plane, c, packed, lane, sK, acc, ring);
+    if (!valid) return;
+    // logical output row 4q + r of class p (register r of quarter q): field q/2,
+    // derivative orders j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2
+    const int fo = q >> 1, o3 = q & 1;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
+        const int j3 = p3 + 2 * o3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j1 = p1 + 2 * (r & 1), j2 = p2 + 2 * (r >> 1);
+            dst[(size_t)(fo * 64 + (j3 * 4 + j2) * 4 + j1) * plane + c.out] = acc[p][r];
+        }
+    }
+}
+
+// Persistent: one workgroup per CU, gridDim.x a multiple of 8. Workgroup b
+// runs on XCD b % 8. Each XCD owns a slab of z-planes; its G/8 workgroups form
+// a block of BY rows (y) x BZ planes (z) that sweeps the slab, one x-row per
+// workgroup per iteration (the 8 waves take the row's 16-cell batches). A node
+// row is read by the cells on both sides of it in y and z; in this order those
+// cells run at the same time on the same XCD, so the second read hits L2
+// instead of coming back from memory one iteration later.
 __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* __restrict__ src,
                                                                  double* __restrict__ dst,
                                                                  const double* __restrict__ Kperm, uint32_t n,
-                                                                 uint32_t off, uint32_t nbatch) {
+                                                                 size_t pitch, uint32_t off) {
     __shared__ double sK[kOpDoubles];
     for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = Kperm[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
-    const uint32_t ncell = n * n * n;
-    const size_t plane = ncell;
-    const uint32_t G = gridDim.x;
-    const uint32_t lb = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
-    const uint32_t per = (nbatch + G - 1) / G;
-    const uint32_t b0 = lb * per;
-    const uint32_t b1 = (b0 + per < nbatch) ? b0 + per : nbatch;
-    for (uint32_t bt = b0 + wave; bt < b1; bt += kWaves) {
-        const uint32_t cell = bt * 16 + cl;
-        const bool valid = cell < ncell;
-        const Cell16 c = cell_nodes(valid ? cell : 0u, n, off);
-        d4 acc[8];
+    const size_t plane = pitch;  // doubles between consecutive columns
+    const uint32_t wpx = gridDim.x / 8;  // workgroups per XCD
+    const uint32_t BZ = (wpx % 4 == 0) ? 4 : (wpx % 2 == 0) ? 2 : 1, BY = wpx / BZ;
+    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t yy = w % BY, zz = w / BY;
+    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
+    const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
+    const uint32_t nbx = (n + 15) / 16;
+    uint32_t packed[8];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
-        double v[8];
-        load_step<0>(src, plane, c, q, v);
-        Steps<0>::run(src, plane, c, q, lane, sK, acc, v);
-        if (!valid) continue;
-        // logical output row 4q + r of class p (register r of quarter q): field q/2,
-        // derivative orders j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2
-        const int fo = q >> 1, o3 = q & 1;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
-            const int j3 = p3 + 2 * o3;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j1 = p1 + 2 * (r & 1), j2 = p2 + 2 * (r >> 1);
-                dst[(size_t)(fo * 64 + (j3 * 4 + j2) * 4 + j1) * plane + c.out] = acc[p][r];
-            }
-        }
+    for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
+    for (uint32_t it = 0; it < nyb * ngr; ++it) {
+        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+        if (y >= n || z >= z1) continue;
+        for (uint32_t bx = wave; bx < nbx; bx += kWaves)
+            run_batch(src, dst, plane, n, off, bx * 16, y, z, lane, cl, q, packed, sK);
     }
 }
 
@@ -186,13 +237,11 @@ void mfma_permute_operators(const double* K, double* Kperm) {
             }
 }
 
-hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, int off, int grid,
-                             hipStream_t st) {
-    const uint32_t ncell = (uint32_t)n * n * n;
-    const uint32_t nbatch = (ncell + 15) / 16;
+hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, size_t pitch, int off,
+                             int grid, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fused_mfma_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Kperm, (uint32_t)n,
-                       (uint32_t)off, nbatch);
+    hipLaunchKernelGGL(fused_mfma_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Kperm, (uint32_t)n, pitch,
+                       (uint32_t)off);
     return hipGetLastError();
 }
 

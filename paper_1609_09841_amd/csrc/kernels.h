@@ -8,34 +8,41 @@
 
 namespace hermite {
 
+// Grids: a two-field grid holds 2 M^3 columns (field-major, then the
+// derivative multi-index d), column c starting at c * pitch doubles; within a
+// column node (i,j,k) sits at (k n + j) n + i. pitch >= n^3 is padded so that
+// the columns of one node do not all fall into the same cache set.
+//
 // One fused half step (interpolation + evolution + truncation per cell) with
 // the per-parity-class operators K ([8][rows_max][2 M^3], FP64). src/dst are
-// two-field grids [2][M^3][n^3]; the cell with lower corner (i,j,k) of src
+// two-field grids; the cell with lower corner (i,j,k) of src
 // writes node (i+off, j+off, k+off) mod n of dst (off = 0 primal->dual,
 // off = 1 dual->primal).
-hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, int off,
+hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, size_t pitch, int off,
                         hipStream_t st);
 
 // Same fused half step on the FP64 matrix cores (m = 3 only). Kperm: the
 // class operators permuted by mfma_permute_operators (mfma_operator_doubles()
 // doubles). grid: workgroups, a multiple of 8 (one per CU is enough).
-hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, int off, int grid,
-                             hipStream_t st);
+hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, size_t pitch, int off,
+                             int grid, hipStream_t st);
 void mfma_permute_operators(const double* K, double* Kperm);
 size_t mfma_operator_doubles();
 
 // Interpolation half of the two-kernel variant: writes the monomial
 // coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity
 // blocks of H, [2][M][M].
-hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, hipStream_t st);
+hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch,
+                         hipStream_t st);
 
 // Evolution half: reads R, runs the Taylor stage loop (evolution 0, q stages)
 // or 4-stage Runge-Kutta (evolution 1, S substeps) with lam = c*tau/h, and
 // writes the coefficients with every index <= m to node cell+off of dst.
-hipError_t launch_evolve(int m, const double* R, double* dst, int n, int off, int evolution, int q,
-                         int S, double lam, hipStream_t st);
+hipError_t launch_evolve(int m, const double* R, double* dst, int n, size_t pitch, int off, int evolution,
+                         int q, int S, double lam, hipStream_t st);
 
-// dst[i] = s * src[i], i < count (dst may equal src).
-hipError_t launch_scale(double* dst, const double* src, double s, size_t count, hipStream_t st);
+// dst[r * dpitch + c] = s * src[r * spitch + c], r < rows, c < cols (dst may equal src).
+hipError_t launch_scale(double* dst, size_t dpitch, const double* src, size_t spitch, double s, size_t cols,
+                        int rows, hipStream_t st);
 
 }  // namespace hermite

@@ -71,14 +71,15 @@ __device__ __forceinline__ double parity_sign(int p, int d) { return ((p + d) & 
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(256) void fused_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                                    const double* __restrict__ K, uint32_t n, uint32_t off) {
+                                                    const double* __restrict__ K, uint32_t n, size_t pitch,
+                                                    uint32_t off) {
     constexpr int M3 = M * M * M, NC = 2 * M3;
     constexpr int RM = 2 * nout_c(M, 0) * nout_c(M, 0) * nout_c(M, 0);
     const uint32_t ncell = n * n * n;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
     if (cell >= ncell) return;
     const CellIdx c = cell_index(cell, n, off);
-    const size_t plane = ncell;
+    const size_t plane = pitch;
     const int pc = blockIdx.y;
     const int p1 = pc & 1, p2 = (pc >> 1) & 1, p3 = pc >> 2;
     const int no1 = nout_c(M, p1), no2 = nout_c(M, p2), no3 = nout_c(M, p3);
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(256) void fused_kernel(const double* __restrict__ s
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(256) void interp_kernel(const double* __restrict__ src, double* __restrict__ R,
-                                                     const double* __restrict__ Hp, uint32_t n) {
+                                                     const double* __restrict__ Hp, uint32_t n, size_t pitch) {
     constexpr int M3 = M * M * M, P = 2 * M, P3 = P * P * P;
     const uint32_t ncell = n * n * n;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void interp_kernel(const double* __restrict__ 
     const double* __restrict__ H1 = Hp + p1 * M * M;
     const double* __restrict__ H2 = Hp + p2 * M * M;
     const double* __restrict__ H3 = Hp + p3 * M * M;
-    const size_t plane = ncell;
+    const size_t plane = pitch;
     const double* __restrict__ srcf = src + (size_t)f * M3 * plane;
     double C[M3], T[M3];
 #pragma unroll
@@ -224,8 +225,8 @@ __device__ __forceinline__ void apply_L(double* Yu, double* Yv, double lam, int 
 
 template <int M>
 __global__ __launch_bounds__(256) void evolve_kernel(const double* __restrict__ R, double* __restrict__ dst,
-                                                     uint32_t n, uint32_t off, int evolution, int q, int S,
-                                                     double lam) {
+                                                     uint32_t n, size_t pitch, uint32_t off, int evolution, int q,
+                                                     int S, double lam) {
     constexpr int G = (M <= 2) ? 2 : 4;
     constexpr int SLOTS = 256 / G;
     constexpr int S2 = M * M, M3 = M * M * M, P = 2 * M, P3 = P * P * P;
@@ -246,9 +247,9 @@ __global__ __launch_bounds__(256) void evolve_kernel(const double* __restrict__ 
 #pragma unroll
         for (int i1 = 0; i1 < M; ++i1) {
             const int k1 = p1 + 2 * i1, k2 = p2 + 2 * i2;
-            const size_t o = (size_t)((k3r * P + k2) * P + k1) * ncell + cc;
+            const size_t o = (size_t)((k3r * P + k2) * P + k1) * pitch + cc;
             Wu[i2 * M + i1] = live ? R[o] : 0.0;
-            Wv[i2 * M + i1] = live ? R[o + (size_t)P3 * ncell] : 0.0;
+            Wv[i2 * M + i1] = live ? R[o + (size_t)P3 * pitch] : 0.0;
         }
     if (evolution == 0) {
         // Alg. 4: W <- R + (1/k) L W for k = q..1 (simultaneous update)
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void evolve_kernel(const double* __restrict__ 
         }
     }
     if (!live || k3 > M - 1) return;
-    const size_t plane = ncell;
+    const size_t plane = pitch;
 #pragma unroll
     for (int i2 = 0; i2 < M; ++i2)
 #pragma unroll
@@ -308,57 +309,67 @@ __global__ __launch_bounds__(256) void evolve_kernel(const double* __restrict__ 
         }
 }
 
-__global__ void scale_kernel(double* __restrict__ dst, const double* __restrict__ src, double s, size_t count) {
+// dst[r * dpitch + c] = s * src[r * spitch + c] for rows r < gridDim.y and
+// columns c < cols (dst may equal src).
+__global__ void scale_kernel(double* __restrict__ dst, size_t dpitch, const double* __restrict__ src, size_t spitch,
+                             double s, size_t cols) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = s * src[i];
+    const double* __restrict__ a = src + (size_t)blockIdx.y * spitch;
+    double* __restrict__ b = dst + (size_t)blockIdx.y * dpitch;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cols; i += stride) b[i] = s * a[i];
 }
 
 }  // namespace
 
-hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, int off, hipStream_t st) {
+hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, size_t pitch, int off,
+                        hipStream_t st) {
     const uint32_t ncell = (uint32_t)n * n * n;
     const dim3 grid((ncell + 255) / 256, 8), block(256);
+    const uint32_t un = (uint32_t)n, uo = (uint32_t)off;
     switch (m) {
-        case 1: hipLaunchKernelGGL(fused_kernel<2>, grid, block, 0, st, src, dst, K, (uint32_t)n, (uint32_t)off); break;
-        case 2: hipLaunchKernelGGL(fused_kernel<3>, grid, block, 0, st, src, dst, K, (uint32_t)n, (uint32_t)off); break;
-        case 3: hipLaunchKernelGGL(fused_kernel<4>, grid, block, 0, st, src, dst, K, (uint32_t)n, (uint32_t)off); break;
+        case 1: hipLaunchKernelGGL(fused_kernel<2>, grid, block, 0, st, src, dst, K, un, pitch, uo); break;
+        case 2: hipLaunchKernelGGL(fused_kernel<3>, grid, block, 0, st, src, dst, K, un, pitch, uo); break;
+        case 3: hipLaunchKernelGGL(fused_kernel<4>, grid, block, 0, st, src, dst, K, un, pitch, uo); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, hipStream_t st) {
+hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch, hipStream_t st) {
     const uint32_t ncell = (uint32_t)n * n * n;
     const dim3 grid((ncell + 255) / 256, 16), block(256);
+    const uint32_t un = (uint32_t)n;
     switch (m) {
-        case 1: hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, st, src, R, Hp, (uint32_t)n); break;
-        case 2: hipLaunchKernelGGL(interp_kernel<3>, grid, block, 0, st, src, R, Hp, (uint32_t)n); break;
-        case 3: hipLaunchKernelGGL(interp_kernel<4>, grid, block, 0, st, src, R, Hp, (uint32_t)n); break;
+        case 1: hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, st, src, R, Hp, un, pitch); break;
+        case 2: hipLaunchKernelGGL(interp_kernel<3>, grid, block, 0, st, src, R, Hp, un, pitch); break;
+        case 3: hipLaunchKernelGGL(interp_kernel<4>, grid, block, 0, st, src, R, Hp, un, pitch); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_evolve(int m, const double* R, double* dst, int n, int off, int evolution, int q, int S,
-                         double lam, hipStream_t st) {
+hipError_t launch_evolve(int m, const double* R, double* dst, int n, size_t pitch, int off, int evolution, int q,
+                         int S, double lam, hipStream_t st) {
     const uint32_t ncell = (uint32_t)n * n * n;
     const int G = (m + 1 <= 2) ? 2 : 4;
     const uint32_t slots = 256 / G;
     const dim3 grid((ncell + slots - 1) / slots, 8), block(256);
     switch (m) {
-        case 1: hipLaunchKernelGGL(evolve_kernel<2>, grid, block, 0, st, R, dst, (uint32_t)n, (uint32_t)off, evolution, q, S, lam); break;
-        case 2: hipLaunchKernelGGL(evolve_kernel<3>, grid, block, 0, st, R, dst, (uint32_t)n, (uint32_t)off, evolution, q, S, lam); break;
-        case 3: hipLaunchKernelGGL(evolve_kernel<4>, grid, block, 0, st, R, dst, (uint32_t)n, (uint32_t)off, evolution, q, S, lam); break;
+        case 1: hipLaunchKernelGGL(evolve_kernel<2>, grid, block, 0, st, R, dst, (uint32_t)n, pitch, (uint32_t)off, evolution, q, S, lam); break;
+        case 2: hipLaunchKernelGGL(evolve_kernel<3>, grid, block, 0, st, R, dst, (uint32_t)n, pitch, (uint32_t)off, evolution, q, S, lam); break;
+        case 3: hipLaunchKernelGGL(evolve_kernel<4>, grid, block, 0, st, R, dst, (uint32_t)n, pitch, (uint32_t)off, evolution, q, S, lam); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_scale(double* dst, const double* src, double s, size_t count, hipStream_t st) {
-    if (count == 0) return hipSuccess;
-    size_t blocks = (count + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, s, count);
+hipError_t launch_scale(double* dst, size_t dpitch, const double* src, size_t spitch, double s, size_t cols,
+                        int rows, hipStream_t st) {
+    if (cols == 0 || rows == 0) return hipSuccess;
+    size_t blocks = (cols + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks, (unsigned)rows), dim3(256), 0, st, dst, dpitch, src, spitch,
+                       s, cols);
     return hipGetLastError();
 }
 
