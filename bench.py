@@ -1,21 +1,32 @@
 """Benchmark of the Hermite wave half step on one MI355X.
 
-Workload: 128^3 periodic cells, m = 3 (64 scaled derivatives per node per
-field), c = 1, cfl = 0.5, u0 = seeded sum of 8 Fourier modes (wave numbers in
-[1, 8], amplitudes ~ N(0, 1)), u_t = 0. One step = one full time step (two
-half steps, primal -> dual -> primal) of the whole grid. The state stays
-resident in HBM; the timed region is hermite_step(K) on the torch stream.
+Workload (headline): 128^3 periodic cells, m = 3 (64 scaled derivatives per
+node per field), c = 1, cfl = 0.5, u0 = seeded sum of 8 Fourier modes (wave
+numbers in [1, 8], amplitudes ~ N(0, 1)), u_t = 0, plain FP64, fused kernel
+with Taylor evolution. One step = one full time step (two half steps,
+primal -> dual -> primal) of the whole grid. The state stays resident in HBM;
+the timed region is hermite_step(K) on a torch stream, between HIP events.
 
-Prints ONE JSON line (rank 0). Metric: DOF-updates/s, a DOF-update being one
-scaled derivative of u or u_t produced on the other grid by one half step:
+Prints ONE JSON line. Metric: DOF-updates/s, a DOF-update being one scaled
+derivative of u or u_t produced on the other grid by one half step:
 value = 2 (m+1)^3 n^3 * 2 K / seconds.
+
+Also reported (outside the timed region of the headline):
+  * the other kernel organisations / evolutions at the same workload;
+  * the mixed-precision contractions (FP32, split BF16x3) at the same
+    workload: rate and error against the FP64 run after the same K steps;
+  * precision study: 256^3 cells, m = 3, 200 steps, final-time rel L2 of the
+    mixed paths against the plain FP64 GPU path (whose parity with the CPU
+    oracle is tested separately);
+  * the CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -24,14 +35,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF-updates/s at m=3, plain FP64 vs mixed-precision at rel L2 <= 1e-6"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 64 FP64 FMA lanes/clk x 2
-FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64, vector and matrix alike
 
 # Useful FP64 flops per cell per half step of the fused formulation: the
 # dense per-parity-class operators (2 flops per nonzero entry; 13,499 / 2,047 /
 # 255 nonzeros for m = 3 / 2 / 1, Taylor and RK4 alike) plus the shared 2x2x2
 # butterfly of the corner data (24 adds per derivative index and field).
 NNZ = {1: 255, 2: 2047, 3: 13499}
+
+# Source files of the m = 3 fused FP64 kernel; traffic counters taken on
+# another version of these files are not reported.
+MFMA_SOURCES = ["fused_mfma.hip", "fused_common.h", "mfma_order.h"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fused_mfma_128cube_m3.md")
 
 
 def fused_flops_per_cell(m: int) -> float:
@@ -41,6 +56,30 @@ def fused_flops_per_cell(m: int) -> float:
 def fused_bytes_per_cell(m: int) -> float:
     # read one two-field node of the old grid, write one of the new grid (FP64)
     return 2.0 * 2 * (m + 1) ** 3 * 8
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in MFMA_SOURCES:
+        with open(os.path.join(ROOT, "paper_1609_09841_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the m = 3 fused FP64 kernel from the committed
+    rocprofv3 summary, if it was taken on the current kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(\w+) = (\S+)$", text, re.M))
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -53,8 +92,10 @@ def parse():
     ap.add_argument("--variant", default="fused-taylor",
                     choices=["fused-taylor", "fused-rk4", "two-taylor", "two-rk4"])
     ap.add_argument("--all-variants", action="store_true", help="also time the other three variants")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-precision-study", action="store_true", help="skip the 256^3 precision study")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=48, help="grid of the oracle's timed sample")
+    ap.add_argument("--cpu-n", type=int, default=96, help="grid of the oracle's timed sample")
     return ap.parse_args()
 
 
@@ -63,15 +104,17 @@ def variant_kwargs(v: str) -> dict:
     return {"fused": fused == "fused", "evolution": evo}
 
 
-def time_variant(B, torch, n, m, u0, ut0, steps, warmup, variant):
+def time_variant(B, torch, n, m, u0, ut0, steps, warmup, variant, precision="fp64"):
     # A stream of our own (default priority): torch's current stream is the
     # null stream, which the library would replace by a private one, and the
     # timing events must sit on the stream the kernels run on.
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    with torch.cuda.stream(stream), B.Solver(n, m, 0.5, 1.0, stream=stream, **variant_kwargs(variant)) as s:
+    with torch.cuda.stream(stream), B.Solver(n, m, 0.5, 1.0, stream=stream, precision=precision,
+                                             **variant_kwargs(variant)) as s:
         s.set_initial(u0, ut0)
         s.step(warmup)
+        s.set_initial(u0, ut0)   # the timed steps start from t = 0
         s.sync()
         torch.cuda.synchronize()
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -89,6 +132,31 @@ def time_variant(B, torch, n, m, u0, ut0, steps, warmup, variant):
         s.sync()
         t_final, nsteps, _ = s.time()
     return ms, wall, u, ut, t_final
+
+
+def errors(I, u, ut, ru, rut) -> dict:
+    """rel L2 against a reference: over all DOFs and over node values (d = 0)."""
+    return {"u": I.rel_l2(u, ru), "u_t": I.rel_l2(ut, rut),
+            "u_nodes": I.rel_l2(u[0, 0, 0], ru[0, 0, 0]), "u_t_nodes": I.rel_l2(ut[0, 0, 0], rut[0, 0, 0])}
+
+
+def precision_study(B, torch, I, n=256, m=3, steps=200) -> dict:
+    """Final-time error of the mixed paths against the plain FP64 GPU path."""
+    u0, ut0 = I.fourier_initial(n, m, device="cuda")
+    ms, _, ru, rut, _ = time_variant(B, torch, n, m, u0, ut0, steps, 0, "fused-taylor", "fp64")
+    out = {"workload": f"{n}^3 cells, m={m}, {steps} steps, same Fourier-mode data",
+           "reference": "plain FP64 fused Taylor on the GPU (parity with the CPU oracle tested at 128^3)",
+           "fp64": {"ms_per_step": ms / steps}}
+    for prec in ("fp32", "bf16x3"):
+        pms, _, u, ut, _ = time_variant(B, torch, n, m, u0, ut0, steps, 0, "fused-taylor", prec)
+        e = errors(I, u, ut, ru, rut)
+        out[prec] = {"ms_per_step": pms / steps, "speedup_vs_fp64": ms / pms, "rel_l2_vs_fp64": e,
+                     "meets_1e-6_all_dofs": max(e["u"], e["u_t"]) <= 1e-6,
+                     "meets_1e-6_node_values": max(e["u_nodes"], e["u_t_nodes"]) <= 1e-6}
+        del u, ut
+    del u0, ut0, ru, rut
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(m: int, n_s: int) -> dict:
@@ -138,18 +206,19 @@ def main():
     launches = 2 * K if args.variant.startswith("fused") else 4 * K
     avg_launch_s = sec / launches
     cells = n ** 3
+    roofline = None
     if args.variant.startswith("fused"):
         flops = fused_flops_per_cell(m) * cells
-        achieved_tflops = flops / avg_launch_s / 1e12
+        achieved = flops / avg_launch_s / 1e12
         mfma = (m == 3)
-        roofline = {"bound": "mfma" if mfma else "alu", "achieved": achieved_tflops,
-                    "peak": FP64_MFMA_PEAK_TFLOPS if mfma else FP64_VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+        traffic = measured_traffic() if (mfma and n == 128) else None
+        roofline = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                     "kernel": "fused_mfma_kernel (FP64 MFMA 16x16x4)" if mfma else f"fused_kernel<{m + 1}> (FP64 VALU)",
                     "avg_launch_ms": avg_launch_s * 1e3,
-                    "hbm_GBps_algorithmic": fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9}
-    else:
-        roofline = None
+                    "algorithmic_bytes_per_launch": fused_bytes_per_cell(m) * cells,
+                    "hbm_GBps_algorithmic": fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9,
+                    "hbm_frac_algorithmic": fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9 / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -171,6 +240,20 @@ def main():
             others[v] = {"value": dof_updates_per_step * K / (vms / 1e3), "ms_per_step": vms / K}
             torch.cuda.empty_cache()
         out["variants"] = others
+    if not args.no_mixed and m == 3 and args.variant == "fused-taylor":
+        mixed = {}
+        for prec in ("fp32", "bf16x3"):
+            pms, _, pu, put, _ = time_variant(B, torch, n, m, u0, ut0, K, W, "fused-taylor", prec)
+            mixed[prec] = {"value": dof_updates_per_step * K / (pms / 1e3), "ms_per_step": pms / K,
+                           "speedup_vs_fp64": ms / pms, "rel_l2_vs_fp64": errors(I, pu, put, u, ut)}
+            del pu, put
+        out["mixed"] = mixed
+    del u, ut
+    torch.cuda.empty_cache()
+    if not args.no_precision_study and m == 3:
+        del u0, ut0
+        torch.cuda.empty_cache()
+        out["precision_study"] = precision_study(B, torch, I)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_n)
     print(json.dumps(out), flush=True)

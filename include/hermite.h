@@ -42,8 +42,15 @@ extern "C" {
 #define HERMITE_ESTATE (-4)       /* call out of order (step/gather before set_initial) */
 #define HERMITE_EUNSUPPORTED (-5) /* valid but unsupported combination of options */
 
-/* arithmetic of the interpolation/evolution contractions; the nodal state
- * and the half-step update are FP64 in every mode */
+/* Arithmetic of the interpolation/evolution contractions. The nodal state,
+ * the corner-mean part of every new value and the half-step update are FP64
+ * in every mode. FP32: the rest of the contraction on FP32 matrix cores with
+ * FP32 accumulation. BF16X3: operator and inputs each split into two BF16
+ * parts, three products accumulated in FP32. FP32 and BF16X3 need m = 3 and
+ * fused = 1 (HERMITE_EUNSUPPORTED otherwise). At m = 3 the monomial-basis
+ * interpolation cancels heavily in the high-order derivatives, so the
+ * rounding of the low-precision modes shows up there first: state the error
+ * against an FP64 run for every use. */
 #define HERMITE_PREC_FP64 0
 #define HERMITE_PREC_FP32 1
 #define HERMITE_PREC_BF16X3 2
@@ -86,8 +93,10 @@ void hermite_default_options(hermite_options *opt);
  *   opt:     NULL for defaults
  *   out:     receives the context; untouched on failure
  * Arguments are validated before any HIP call: invalid arguments return
- * HERMITE_EINVAL even without a device. Allocates two FP64 grids of
- * 2*(m+1)^3*n^3 doubles each, plus 2*(2m+2)^3*n^3 doubles when fused == 0.
+ * HERMITE_EINVAL (HERMITE_EUNSUPPORTED for a valid but unsupported option
+ * combination) even without a device. Allocates two FP64 grids of
+ * 2*(m+1)^3 columns of n^3 doubles each, plus 2*(2m+2)^3 columns when
+ * fused == 0; each device column is padded by at most 112 doubles.
  * No kernel runs.
  */
 int hermite_create(int n_cells, int m, double cfl, double c,

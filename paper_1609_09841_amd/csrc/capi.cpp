@@ -29,11 +29,12 @@ struct hermite_ctx {
     int device = 0;
     int cus = 0;             // compute units of the device (persistent grids)
     bool use_mfma = false;   // m = 3 fused FP64 on the matrix cores
+    int precision = 0;       // HERMITE_PREC_*: contraction arithmetic
     double* grid[2] = {nullptr, nullptr};  // primal, dual: 2 M^3 columns of `pitch` doubles each
     double* R = nullptr;                   // two-kernel scratch: 2 P^3 columns of `pitch` doubles
     size_t ncell = 0;                      // n^3 nodes per column
     size_t pitch = 0;                      // doubles between consecutive columns (>= ncell)
-    double* K = nullptr;                   // fused class operators
+    void* K = nullptr;                     // fused class operators (layout of the kernel in use)
     double* Hp = nullptr;                  // parity blocks of H
     size_t grid_doubles = 0;
     bool has_state = false;
@@ -96,11 +97,14 @@ int half_step(hermite_ctx* ctx, int from) {
         HCHECK(ctx, hipMemsetAsync(dst, 0xFF, ctx->grid_doubles * sizeof(double), ctx->stream), "poison");
     hipError_t e;
     if (ctx->opt.fused) {
-        if (ctx->use_mfma) {
-            const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
-            e = hermite::launch_fused_mfma(src, dst, ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
+        const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
+        if (ctx->precision != HERMITE_PREC_FP64) {
+            e = hermite::launch_fused_mixed(ctx->precision, src, dst, ctx->K, ctx->n, ctx->pitch, off, grid,
+                                            ctx->stream);
+        } else if (ctx->use_mfma) {
+            e = hermite::launch_fused_mfma(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
         } else {
-            e = hermite::launch_fused(ctx->m, src, dst, ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
+            e = hermite::launch_fused(ctx->m, src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "fused half-step launch");
     } else {
@@ -146,8 +150,9 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     if (o.q < 0 || o.q > 64) return fail(nullptr, HERMITE_EINVAL, "q=%d outside [0, 64]", o.q);
     if (o.fused != 0 && o.fused != 1) return fail(nullptr, HERMITE_EINVAL, "fused=%d", o.fused);
     if (o.poison != 0 && o.poison != 1) return fail(nullptr, HERMITE_EINVAL, "poison=%d", o.poison);
-    if (o.precision != HERMITE_PREC_FP64)
-        return fail(nullptr, HERMITE_EUNSUPPORTED, "precision=%d is not available in this build", o.precision);
+    if (o.precision != HERMITE_PREC_FP64 && (m != 3 || !o.fused))
+        return fail(nullptr, HERMITE_EUNSUPPORTED,
+                    "precision=%d needs m = 3 and the fused kernel (m=%d, fused=%d)", o.precision, m, o.fused);
 
     const int M = m + 1, P = 2 * m + 2;
     const size_t nn = (size_t)n_cells * n_cells * n_cells;
@@ -207,17 +212,23 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     // The m = 3 fused FP64 half step runs on the matrix cores unless
     // HERMITE_FUSED_KERNEL=valu asks for the vector kernel (comparison runs).
     const char* kern = std::getenv("HERMITE_FUSED_KERNEL");
+    ctx->precision = o.precision;
     ctx->use_mfma = (m == 3) && o.fused && !(kern && std::strcmp(kern, "valu") == 0);
-    std::vector<double> Kdev;
-    if (ctx->use_mfma) {
-        Kdev.resize(hermite::mfma_operator_doubles());
-        hermite::mfma_permute_operators(K.data(), Kdev.data());
+    std::vector<unsigned char> Kdev;
+    if (o.precision != HERMITE_PREC_FP64) {
+        Kdev.resize(hermite::mixed_operator_bytes(o.precision));
+        hermite::mixed_build_operators(o.precision, K.data(), Kdev.data());
+    } else if (ctx->use_mfma) {
+        Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
+        hermite::mfma_permute_operators(K.data(), (double*)Kdev.data());
     } else {
-        Kdev = hermite::fused_operators_by_column(m, K);
+        const std::vector<double> Kc = hermite::fused_operators_by_column(m, K);
+        Kdev.resize(Kc.size() * sizeof(double));
+        std::memcpy(Kdev.data(), Kc.data(), Kdev.size());
     }
-    e = hipMalloc(&ctx->K, Kdev.size() * sizeof(double));
+    e = hipMalloc(&ctx->K, Kdev.size());
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));
-    e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size() * sizeof(double), hipMemcpyHostToDevice);
+    e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
     e = hipMalloc(&ctx->Hp, Hp.size() * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(Hp)"));

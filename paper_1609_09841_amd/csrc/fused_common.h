@@ -1,0 +1,130 @@
+// Device building blocks shared by the matrix-core fused half-step kernels
+// (m = 3): cell corner addressing, the 2x2x2 parity butterfly of the corner
+// data and the XCD-blocked sweep over the grid.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hermite {
+namespace fused {
+
+// The 8 corner nodes of one cell, s = s1 + 2 s2 + 4 s3, and the node of the
+// other grid that the cell writes.
+struct Cell16 {
+    uint32_t corner[8];
+    uint32_t out;
+};
+
+// Cell with lower corner (i, j, k) = flat index (k n + j) n + i, periodic in
+// every axis; off = 0 writes node (i, j, k) (primal -> dual), off = 1 writes
+// (i+1, j+1, k+1) mod n (dual -> primal).
+__device__ __forceinline__ Cell16 cell_nodes(uint32_t cell, uint32_t n, uint32_t off) {
+    const uint32_t i = cell % n, t = cell / n, j = t % n, k = t / n;
+    const uint32_t i1 = (i + 1 == n) ? 0 : i + 1, j1 = (j + 1 == n) ? 0 : j + 1, k1 = (k + 1 == n) ? 0 : k + 1;
+    Cell16 c;
+    const uint32_t xs[2] = {i, i1}, ys[2] = {j, j1}, zs[2] = {k, k1};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) c.corner[s] = (zs[s >> 2] * n + ys[(s >> 1) & 1]) * n + xs[s & 1];
+    c.out = ((off ? k1 : k) * n + (off ? j1 : j)) * n + (off ? i1 : i);
+    return c;
+}
+
+// Butterfly of the 8 corner values v[s1 + 2 s2 + 4 s3] of one derivative
+// multi-index: T[t1 + 2 t2 + 4 t3] = sum_s prod_x (t_x ? (s_x ? 1 : -1) : 1) v[s]
+// (t_x = 1: right minus left along x, t_x = 0: right plus left). Parity class
+// p takes output t = p xor (d mod 2) of the butterfly of index d.
+__device__ __forceinline__ void butterfly8(const double* v, double* T) {
+    double a[8], b[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a[2 * q] = v[2 * q + 1] + v[2 * q];
+        a[2 * q + 1] = v[2 * q + 1] - v[2 * q];
+    }
+    // a index: t1 + 2*(s2 + 2 s3)
+#pragma unroll
+    for (int s3 = 0; s3 < 2; ++s3)
+#pragma unroll
+        for (int t1 = 0; t1 < 2; ++t1) {
+            const double l = a[t1 + 2 * (0 + 2 * s3)], r = a[t1 + 2 * (1 + 2 * s3)];
+            b[t1 + 2 * 0 + 4 * s3] = r + l;
+            b[t1 + 2 * 1 + 4 * s3] = r - l;
+        }
+    // b index: t1 + 2 t2 + 4 s3
+#pragma unroll
+    for (int t12 = 0; t12 < 4; ++t12) {
+        const double l = b[t12], r = b[t12 + 4];
+        T[t12] = r + l;
+        T[t12 + 4] = r - l;
+    }
+}
+
+// Persistent sweep: one workgroup per CU, gridDim.x a multiple of 8, and
+// workgroup b runs on XCD b % 8. Each XCD owns a slab of z-planes; its G/8
+// workgroups form a block of BY rows (y) x BZ planes (z) that sweeps the
+// slab, one x-row per workgroup per iteration, the waves of the workgroup
+// taking the row's 16-cell batches. A node row is read by the cells on both
+// sides of it in y and z; in this order those cells run at the same time on
+// the same XCD, so the second read hits L2 instead of coming back from memory
+// one iteration later. f(x0, y, z) runs the batch of cells x0 .. x0+15 of row
+// (y, z).
+template <class F>
+__device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& f) {
+    const uint32_t wpx = gridDim.x / 8;  // workgroups per XCD
+    const uint32_t BZ = (wpx % 4 == 0) ? 4 : (wpx % 2 == 0) ? 2 : 1, BY = wpx / BZ;
+    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t yy = w % BY, zz = w / BY;
+    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
+    const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
+    const uint32_t nbx = (n + 15) / 16;
+    for (uint32_t it = 0; it < nyb * ngr; ++it) {
+        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+        if (y >= n || z >= z1) continue;
+        for (uint32_t bx = wave; bx < nbx; bx += waves) f(bx * 16, y, z);
+    }
+}
+
+// Same order for kernels whose workgroup computes a segment of up to `seg`
+// cells of one x-row together: f(x0, y, z) runs cells x0 .. x0+seg-1 of row
+// (y, z) (fewer at the end of the row) and is called by every thread of the
+// workgroup the same number of times (f may synchronise the workgroup).
+template <class F>
+__device__ __forceinline__ void sweep_segments(uint32_t n, uint32_t seg, F&& f) {
+    const uint32_t wpx = gridDim.x / 8;
+    const uint32_t BZ = (wpx % 4 == 0) ? 4 : (wpx % 2 == 0) ? 2 : 1, BY = wpx / BZ;
+    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t yy = w % BY, zz = w / BY;
+    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
+    const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
+    const uint32_t nsx = (n + seg - 1) / seg;
+    for (uint32_t it = 0; it < nyb * ngr; ++it) {
+        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+        if (y >= n || z >= z1) continue;
+        for (uint32_t sx = 0; sx < nsx; ++sx) f(sx * seg, y, z);
+    }
+}
+
+// Input-column schedule of the mixed-precision kernels: lane quarter q reads
+// the columns of field q/2 with d3 in {2 (q%2), 2 (q%2) + 1}, which are exactly
+// the 32 new values (of field q/2 and o3 = q%2) that its accumulators hold.
+// Step t reads column 32 q + u[t], u = 16 b3 + 4 d2 + d1 (d3 = 2 (q%2) + b3),
+// in order of decreasing b3 + d2 + d1. The parity pattern of d, and so the
+// butterfly output that feeds each class, depends on t only.
+struct OwnSchedule {
+    int u[32];
+    constexpr OwnSchedule() : u() {
+        int t = 0;
+        for (int s = 7; s >= 0; --s)
+            for (int b3 = 0; b3 < 2; ++b3)
+                for (int d2 = 0; d2 < 4; ++d2)
+                    for (int d1 = 0; d1 < 4; ++d1)
+                        if (b3 + d2 + d1 == s) u[t++] = 16 * b3 + 4 * d2 + d1;
+    }
+    static constexpr int parity(int u) { return (u & 1) | (((u >> 2) & 1) << 1) | ((u >> 4) << 2); }
+    // accumulator register (o2, o1) of the new value j = d read at u
+    static constexpr int reg(int u) { return ((u >> 3) & 1) * 2 + ((u >> 1) & 1); }
+};
+
+}  // namespace fused
+}  // namespace hermite

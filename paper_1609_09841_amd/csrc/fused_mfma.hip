@@ -23,60 +23,21 @@
 
 #include <cstdint>
 
+#include "fused_common.h"
 #include "kernels.h"
 #include "mfma_order.h"
 
 namespace hermite {
 namespace {
 
+using fused::butterfly8;
+using fused::Cell16;
+using fused::cell_nodes;
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8;                 // waves per workgroup (2 per SIMD)
 constexpr int kOpDoubles = 8 * 32 * 64;   // class operators in lane order
-
-struct Cell16 {
-    uint32_t corner[8];
-    uint32_t out;
-};
-
-__device__ __forceinline__ Cell16 cell_nodes(uint32_t cell, uint32_t n, uint32_t off) {
-    const uint32_t i = cell % n, t = cell / n, j = t % n, k = t / n;
-    const uint32_t i1 = (i + 1 == n) ? 0 : i + 1, j1 = (j + 1 == n) ? 0 : j + 1, k1 = (k + 1 == n) ? 0 : k + 1;
-    Cell16 c;
-    const uint32_t xs[2] = {i, i1}, ys[2] = {j, j1}, zs[2] = {k, k1};
-#pragma unroll
-    for (int s = 0; s < 8; ++s) c.corner[s] = (zs[s >> 2] * n + ys[(s >> 1) & 1]) * n + xs[s & 1];
-    c.out = ((off ? k1 : k) * n + (off ? j1 : j)) * n + (off ? i1 : i);
-    return c;
-}
-
-// Butterfly of the 8 corner values v[s1 + 2 s2 + 4 s3] of one derivative
-// multi-index: T[t1 + 2 t2 + 4 t3] = sum_s prod_x (t_x ? (s_x ? 1 : -1) : 1) v[s]
-// (t_x = 1: right minus left along x, t_x = 0: right plus left).
-__device__ __forceinline__ void butterfly8(const double* v, double* T) {
-    double a[8], b[8];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        a[2 * q] = v[2 * q + 1] + v[2 * q];
-        a[2 * q + 1] = v[2 * q + 1] - v[2 * q];
-    }
-    // a index: t1 + 2*(s2 + 2 s3)
-#pragma unroll
-    for (int s3 = 0; s3 < 2; ++s3)
-#pragma unroll
-        for (int t1 = 0; t1 < 2; ++t1) {
-            const double l = a[t1 + 2 * (0 + 2 * s3)], r = a[t1 + 2 * (1 + 2 * s3)];
-            b[t1 + 2 * 0 + 4 * s3] = r + l;
-            b[t1 + 2 * 1 + 4 * s3] = r - l;
-        }
-    // b index: t1 + 2 t2 + 4 s3
-#pragma unroll
-    for (int t12 = 0; t12 < 4; ++t12) {
-        const double l = b[t12], r = b[t12 + 4];
-        T[t12] = r + l;
-        T[t12 + 4] = r - l;
-    }
-}
 
 // Input column of step T for this lane, from the lane's packed column table
 // (four 7-bit column numbers per word, filled once per kernel): branch-free,
@@ -182,13 +143,7 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     }
 }
 
-// Persistent: one workgroup per CU, gridDim.x a multiple of 8. Workgroup b
-// runs on XCD b % 8. Each XCD owns a slab of z-planes; its G/8 workgroups form
-// a block of BY rows (y) x BZ planes (z) that sweeps the slab, one x-row per
-// workgroup per iteration (the 8 waves take the row's 16-cell batches). A node
-// row is read by the cells on both sides of it in y and z; in this order those
-// cells run at the same time on the same XCD, so the second read hits L2
-// instead of coming back from memory one iteration later.
+// Persistent kernel over the XCD-blocked row sweep (fused::sweep_rows).
 __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* __restrict__ src,
                                                                  double* __restrict__ dst,
                                                                  const double* __restrict__ Kperm, uint32_t n,
@@ -198,23 +153,12 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* _
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
-    const size_t plane = pitch;  // doubles between consecutive columns
-    const uint32_t wpx = gridDim.x / 8;  // workgroups per XCD
-    const uint32_t BZ = (wpx % 4 == 0) ? 4 : (wpx % 2 == 0) ? 2 : 1, BY = wpx / BZ;
-    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
-    const uint32_t yy = w % BY, zz = w / BY;
-    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
-    const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
-    const uint32_t nbx = (n + 15) / 16;
     uint32_t packed[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
-    for (uint32_t it = 0; it < nyb * ngr; ++it) {
-        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
-        if (y >= n || z >= z1) continue;
-        for (uint32_t bx = wave; bx < nbx; bx += kWaves)
-            run_batch(src, dst, plane, n, off, bx * 16, y, z, lane, cl, q, packed, sK);
-    }
+    fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
+        run_batch(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
+    });
 }
 
 }  // namespace

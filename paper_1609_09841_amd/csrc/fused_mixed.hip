@@ -1,0 +1,252 @@
+// Mixed-precision fused Hermite half step for m = 3 (FP32 or split-BF16
+// contractions on the matrix cores, FP64 state and FP64 update).
+//
+// The half step of a cell is, per parity class p, y = K_p x with x the 128
+// class inputs (the 2x2x2 butterfly of the corner data, formed in FP64) and
+// y the 16 new values of that class. Most of each new value is the mean of
+// its own scaled derivative over the 8 corners: for the new value j of field
+// f, P0 = (1/8) x[(f, d = j)], the all-sums butterfly output of column
+// (f, j). So the kernel keeps P0 in FP64 and runs only the remainder
+// (K_p - P0) x in low precision:
+//   y = P0 (FP64) + [(K_p - P0) x] (FP32 accumulation) -> FP64 store.
+// Which lane computes which P0: lane quarter q reads exactly the 32 columns
+// whose new values its accumulators hold (fused::OwnSchedule), so P0 is a
+// register of the lane that holds the output.
+//
+// FP32: v_mfma_f32_16x16x4f32, one K-step per input column chunk, the same
+// shape as the FP64 kernel (A = operator rows x 4 columns, B = 4 columns x 16
+// cells; register r of lane quarter q holds row 4q + r).
+// BF16x3: v_mfma_f32_16x16x16_bf16 over 8 K-steps of 16 columns (lane
+// quarter q supplies k = 4q .. 4q+3). Operator and inputs are split into a
+// high and a low BF16 part (x = x_hi + x_lo, each round-to-nearest-even) and
+// the three products lo*hi, hi*lo, hi*hi are accumulated in FP32; the lo*lo
+// term is dropped (relative weight 2^-16 and below).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "fused_common.h"
+#include "kernels.h"
+
+namespace hermite {
+namespace {
+
+using fused::butterfly8;
+using fused::Cell16;
+using fused::cell_nodes;
+using fused::OwnSchedule;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));  // 4 BF16 bit patterns
+
+constexpr int kWaves = 8;
+// software-pipeline depth (steps whose corner loads are in flight) per
+// precision: the BF16 path keeps two split input buffers live and has
+// registers for one step ahead only
+template <int PREC>
+constexpr int kAhead = (PREC == 1) ? 2 : 1;
+constexpr int kRing = 3;
+constexpr int kF32Floats = 8 * 32 * 64;      // [class][step][lane]
+constexpr int kBf16Vecs = 8 * 8 * 2 * 64;    // [class][K-step][hi/lo][lane] of 4 BF16
+
+// Corner values of step T: column 32 q + u[T]; `base` is src + 32 q pitch.
+template <int T>
+__device__ __forceinline__ void load_own(const double* __restrict__ base, size_t pitch, const Cell16& c, double* v) {
+    constexpr OwnSchedule S{};
+    const double* __restrict__ b = base + (size_t)S.u[T] * pitch;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = b[c.corner[s]];
+}
+
+template <int AH, int T>
+struct Prologue {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& c,
+                                               double (*ring)[8]) {
+        load_own<T>(base, pitch, c, ring[T]);
+        if constexpr (T + 1 < AH) Prologue<AH, T + 1>::run(base, pitch, c, ring);
+    }
+};
+
+// ---------------------------------------------------------------- FP32
+template <int T>
+struct StepsF32 {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& c,
+                                               int lane, const float* sA, f4* acc, double (*P0)[4],
+                                               double (*ring)[8]) {
+        constexpr OwnSchedule S{};
+        constexpr int u = S.u[T], dp = OwnSchedule::parity(u), rg = OwnSchedule::reg(u);
+        constexpr int AH = kAhead<1>;
+        if constexpr (T + AH < 32) load_own<T + AH>(base, pitch, c, ring[(T + AH) % kRing]);
+        double Tv[8];
+        butterfly8(ring[T % kRing], Tv);
+        P0[dp][rg] = 0.125 * Tv[0];
+        float a[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) a[p] = sA[(p * 32 + T) * 64 + lane];
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p], (float)Tv[p ^ dp], acc[p], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (T + 1 < 32) StepsF32<T + 1>::run(base, pitch, c, lane, sA, acc, P0, ring);
+    }
+};
+
+// ---------------------------------------------------------------- BF16x3
+template <int T>
+struct StepsBf16 {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& c,
+                                               int lane, const s4* sA, f4* acc, double (*P0)[4],
+                                               double (*ring)[8], s4* Bhi, s4* Blo) {
+        constexpr OwnSchedule S{};
+        constexpr int u = S.u[T], dp = OwnSchedule::parity(u), rg = OwnSchedule::reg(u);
+        constexpr int ks = T / 4, e = T % 4;
+        constexpr int AH = kAhead<2>;
+        if constexpr (T + AH < 32) load_own<T + AH>(base, pitch, c, ring[(T + AH) % kRing]);
+        double Tv[8];
+        butterfly8(ring[T % kRing], Tv);
+        P0[dp][rg] = 0.125 * Tv[0];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const float x = (float)Tv[p ^ dp];
+            const __bf16 hi = (__bf16)x;  // round to nearest even
+            Bhi[p][e] = __builtin_bit_cast(short, hi);
+            Blo[p][e] = __builtin_bit_cast(short, (__bf16)(x - (float)hi));
+        }
+        if constexpr (e == 3) {
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                const s4 ahi = sA[((p * 8 + ks) * 2 + 0) * 64 + lane];
+                const s4 alo = sA[((p * 8 + ks) * 2 + 1) * 64 + lane];
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, Bhi[p], acc[p], 0, 0, 0);
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Blo[p], acc[p], 0, 0, 0);
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Bhi[p], acc[p], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (T + 1 < 32) StepsBf16<T + 1>::run(base, pitch, c, lane, sA, acc, P0, ring, Bhi, Blo);
+    }
+};
+
+// y = P0 + (double) acc; register r of quarter q of class p is the new value
+// of field q/2 with derivative orders j = p + 2 (r % 2, r / 2, q % 2).
+__device__ __forceinline__ void store_batch(double* __restrict__ dst, size_t plane, const Cell16& c, int q,
+                                            const f4* acc, double (*P0)[4]) {
+    const int fo = q >> 1, o3 = q & 1;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
+        const int j3 = p3 + 2 * o3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j1 = p1 + 2 * (r & 1), j2 = p2 + 2 * (r >> 1);
+            dst[(size_t)(fo * 64 + (j3 * 4 + j2) * 4 + j1) * plane + c.out] = P0[p][r] + (double)acc[p][r];
+        }
+    }
+}
+
+template <int PREC>  // 1 = FP32, 2 = BF16x3
+__global__ __launch_bounds__(kWaves * 64) void fused_mixed_kernel(const double* __restrict__ src,
+                                                                  double* __restrict__ dst,
+                                                                  const void* __restrict__ Aops, uint32_t n,
+                                                                  size_t pitch, uint32_t off) {
+    constexpr int kBytes = (PREC == 1) ? kF32Floats * 4 : kBf16Vecs * 8;
+    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kBytes];
+    {
+        const uint4* g = (const uint4*)Aops;
+        uint4* l = (uint4*)sbuf;
+        for (int i = threadIdx.x; i < kBytes / 16; i += blockDim.x) l[i] = g[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
+        const uint32_t x = x0 + cl;
+        const bool valid = x < n;
+        const Cell16 c = cell_nodes((z * n + y) * n + (valid ? x : n - 1), n, off);
+        const double* base = src + (size_t)(32 * q) * pitch;
+        // opaque per batch, so per-step addresses are not hoisted out of the sweep
+        asm volatile("" : "+v"(base));
+        f4 acc[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
+        double P0[8][4];
+        double ring[kRing][8];
+        Prologue<kAhead<PREC>, 0>::run(base, pitch, c, ring);
+        if constexpr (PREC == 1) {
+            StepsF32<0>::run(base, pitch, c, lane, (const float*)sbuf, acc, P0, ring);
+        } else {
+            s4 Bhi[8], Blo[8];
+            StepsBf16<0>::run(base, pitch, c, lane, (const s4*)sbuf, acc, P0, ring, Bhi, Blo);
+        }
+        if (valid) store_batch(dst, pitch, c, q, acc, P0);
+    });
+}
+
+uint16_t bf16_rne(float f) {
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+float bf16_to_float(uint16_t h) {
+    const uint32_t b = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+}  // namespace
+
+size_t mixed_operator_bytes(int precision) {
+    return precision == 1 ? (size_t)kF32Floats * 4 : precision == 2 ? (size_t)kBf16Vecs * 8 : 0;
+}
+
+void mixed_build_operators(int precision, const double* K, void* out) {
+    // K: [8][16][128] canonical class operators (rows (fo, o3, o2, o1), columns
+    // f*64 + dd). Remainder operator K' = K - P0: the new value j of field fo
+    // (row (fo, o), j = p + 2o) loses 1/8 on its own column (fo, d = j).
+    constexpr OwnSchedule S{};
+    auto kr = [&](int p, int row, int col) {
+        const int fo = row >> 3, o3 = (row >> 2) & 1, o2 = (row >> 1) & 1, o1 = row & 1;
+        const int j1 = (p & 1) + 2 * o1, j2 = ((p >> 1) & 1) + 2 * o2, j3 = (p >> 2) + 2 * o3;
+        const int own = fo * 64 + (j3 * 4 + j2) * 4 + j1;
+        return K[((size_t)p * 16 + row) * 128 + col] - (col == own ? 0.125 : 0.0);
+    };
+    if (precision == 1) {
+        float* A = (float*)out;
+        for (int p = 0; p < 8; ++p)
+            for (int t = 0; t < 32; ++t)
+                for (int lane = 0; lane < 64; ++lane)
+                    A[((size_t)p * 32 + t) * 64 + lane] = (float)kr(p, lane & 15, 32 * (lane >> 4) + S.u[t]);
+    } else {
+        uint16_t* A = (uint16_t*)out;
+        for (int p = 0; p < 8; ++p)
+            for (int ks = 0; ks < 8; ++ks)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int e = 0; e < 4; ++e) {
+                        const double v = kr(p, lane & 15, 32 * (lane >> 4) + S.u[4 * ks + e]);
+                        const uint16_t hi = bf16_rne((float)v);
+                        const uint16_t lo = bf16_rne((float)(v - (double)bf16_to_float(hi)));
+                        A[((((size_t)p * 8 + ks) * 2 + 0) * 64 + lane) * 4 + e] = hi;
+                        A[((((size_t)p * 8 + ks) * 2 + 1) * 64 + lane) * 4 + e] = lo;
+                    }
+    }
+}
+
+hipError_t launch_fused_mixed(int precision, const double* src, double* dst, const void* Aops, int n, size_t pitch,
+                              int off, int grid, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
+    if (precision == 1)
+        hipLaunchKernelGGL(fused_mixed_kernel<1>, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Aops, (uint32_t)n,
+                           pitch, (uint32_t)off);
+    else if (precision == 2)
+        hipLaunchKernelGGL(fused_mixed_kernel<2>, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Aops, (uint32_t)n,
+                           pitch, (uint32_t)off);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace hermite

@@ -29,6 +29,15 @@ hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm
 void mfma_permute_operators(const double* K, double* Kperm);
 size_t mfma_operator_doubles();
 
+// Mixed-precision fused half step (m = 3): precision 1 = FP32 matrix cores,
+// 2 = split BF16 (three products), both with FP32 accumulation; FP64 state,
+// FP64 corner-mean part and FP64 update. Aops: mixed_build_operators output
+// (mixed_operator_bytes(precision) bytes). grid as for launch_fused_mfma.
+hipError_t launch_fused_mixed(int precision, const double* src, double* dst, const void* Aops, int n, size_t pitch,
+                              int off, int grid, hipStream_t st);
+size_t mixed_operator_bytes(int precision);
+void mixed_build_operators(int precision, const double* K, void* out);
+
 // Interpolation half of the two-kernel variant: writes the monomial
 // coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity
 // blocks of H, [2][M][M].

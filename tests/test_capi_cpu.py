@@ -100,3 +100,15 @@ def test_valid_create_without_device_reports_device_error():
     rc, h = B.hermite_create(8, 2, 0.5, 1.0)
     assert rc == B.HERMITE_EDEVICE and h is None
     assert B.hermite_last_error(None) != ""
+
+
+@pytest.mark.parametrize("m,fused", [(1, 1), (2, 1), (3, 0)])
+@pytest.mark.parametrize("precision", [B.HERMITE_PREC_FP32, B.HERMITE_PREC_BF16X3])
+def test_mixed_precision_needs_m3_fused(precision, m, fused):
+    """FP32 / BF16x3 contractions exist for the m = 3 fused kernel only; other
+    combinations are refused before any device call."""
+    o = B.hermite_default_options()
+    o.precision, o.fused = precision, fused
+    rc, h = B.hermite_create(8, m, 0.5, 1.0, o)
+    assert rc == B.HERMITE_EUNSUPPORTED and h is None
+    assert "precision" in B.hermite_last_error(None)
