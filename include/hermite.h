@@ -55,6 +55,13 @@ extern "C" {
 #define HERMITE_PREC_FP32 1
 #define HERMITE_PREC_BF16X3 2
 
+/* Kernel of the fused FP64 half step at m = 3 (ignored otherwise). Both
+ * compute the same contraction in FP64 with the same operator; on gfx950 the
+ * matrix-core kernel is the faster one. */
+#define HERMITE_KERNEL_AUTO 0  /* the matrix-core kernel */
+#define HERMITE_KERNEL_MFMA 1  /* FP64 matrix cores (v_mfma_f64_16x16x4) */
+#define HERMITE_KERNEL_VALU 2  /* FP64 vector FMAs, operator entries as scalar operands */
+
 #define HERMITE_EVOLVE_TAYLOR 0 /* Sec. 3.2, Alg. 4: q-stage Taylor series (Horner) */
 #define HERMITE_EVOLVE_RK4 1    /* classical 4-stage Runge-Kutta on the cell ODE */
 
@@ -73,6 +80,7 @@ typedef struct hermite_options {
                         (Sec. 3.1-3.2, two kernels) */
     int poison;      /* debug: 1 fills each destination grid with NaN before
                         the half step that writes it */
+    int kernel;      /* fused FP64 kernel for m = 3: HERMITE_KERNEL_* */
     void *stream;    /* hipStream_t to run on; NULL -> a stream owned by the
                         context. Caller keeps a given stream alive until
                         hermite_destroy. */

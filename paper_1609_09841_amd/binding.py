@@ -26,6 +26,10 @@ HERMITE_PREC_FP32 = 1
 HERMITE_PREC_BF16X3 = 2
 HERMITE_EVOLVE_TAYLOR = 0
 HERMITE_EVOLVE_RK4 = 1
+HERMITE_KERNEL_AUTO = 0
+HERMITE_KERNEL_MFMA = 1
+HERMITE_KERNEL_VALU = 2
+KERNELS = {"auto": HERMITE_KERNEL_AUTO, "mfma": HERMITE_KERNEL_MFMA, "valu": HERMITE_KERNEL_VALU}
 
 PRECISIONS = {"fp64": HERMITE_PREC_FP64, "fp32": HERMITE_PREC_FP32, "bf16x3": HERMITE_PREC_BF16X3}
 EVOLUTIONS = {"taylor": HERMITE_EVOLVE_TAYLOR, "rk4": HERMITE_EVOLVE_RK4}
@@ -46,6 +50,7 @@ class hermite_options(ctypes.Structure):
         ("q", ctypes.c_int),
         ("fused", ctypes.c_int),
         ("poison", ctypes.c_int),
+        ("kernel", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -134,7 +139,7 @@ class Solver:
 
     def __init__(self, n: int, m: int, cfl: float = 0.5, c: float = 1.0, *, precision: str = "fp64",
                  evolution: str = "taylor", q: int = 0, rk_substeps: int = 1, fused: bool = True,
-                 poison: bool = False, stream=None):
+                 poison: bool = False, kernel: str = "auto", stream=None):
         lib = load()
         o = hermite_default_options()
         o.precision = PRECISIONS[precision]
@@ -143,6 +148,7 @@ class Solver:
         o.rk_substeps = int(rk_substeps)
         o.fused = int(bool(fused))
         o.poison = int(bool(poison))
+        o.kernel = KERNELS[kernel]
         if stream is not None:
             o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
         self.n, self.m = int(n), int(m)

@@ -28,7 +28,7 @@ struct hermite_ctx {
     bool own_stream = false;
     int device = 0;
     int cus = 0;             // compute units of the device (persistent grids)
-    bool use_mfma = false;   // m = 3 fused FP64 on the matrix cores
+    int m3_kernel = 0;       // m = 3 fused FP64: 0 vector ALUs, 1 matrix cores
     int precision = 0;       // HERMITE_PREC_*: contraction arithmetic
     double* grid[2] = {nullptr, nullptr};  // primal, dual: 2 M^3 columns of `pitch` doubles each
     double* R = nullptr;                   // two-kernel scratch: 2 P^3 columns of `pitch` doubles
@@ -101,8 +101,10 @@ int half_step(hermite_ctx* ctx, int from) {
         if (ctx->precision != HERMITE_PREC_FP64) {
             e = hermite::launch_fused_mixed(ctx->precision, src, dst, ctx->K, ctx->n, ctx->pitch, off, grid,
                                             ctx->stream);
-        } else if (ctx->use_mfma) {
+        } else if (ctx->m == 3 && ctx->m3_kernel == 1) {
             e = hermite::launch_fused_mfma(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
+        } else if (ctx->m == 3) {
+            e = hermite::launch_fused_valu4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         } else {
             e = hermite::launch_fused(ctx->m, src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         }
@@ -130,6 +132,7 @@ void hermite_default_options(hermite_options* opt) {
     opt->q = 0;
     opt->fused = 1;
     opt->poison = 0;
+    opt->kernel = HERMITE_KERNEL_AUTO;
     opt->stream = nullptr;
 }
 
@@ -150,6 +153,8 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     if (o.q < 0 || o.q > 64) return fail(nullptr, HERMITE_EINVAL, "q=%d outside [0, 64]", o.q);
     if (o.fused != 0 && o.fused != 1) return fail(nullptr, HERMITE_EINVAL, "fused=%d", o.fused);
     if (o.poison != 0 && o.poison != 1) return fail(nullptr, HERMITE_EINVAL, "poison=%d", o.poison);
+    if (o.kernel < HERMITE_KERNEL_AUTO || o.kernel > HERMITE_KERNEL_VALU)
+        return fail(nullptr, HERMITE_EINVAL, "kernel=%d", o.kernel);
     if (o.precision != HERMITE_PREC_FP64 && (m != 3 || !o.fused))
         return fail(nullptr, HERMITE_EUNSUPPORTED,
                     "precision=%d needs m = 3 and the fused kernel (m=%d, fused=%d)", o.precision, m, o.fused);
@@ -209,18 +214,18 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     const std::vector<double> K = hermite::fused_class_operators(m, ctx->lam, cpoly);
     e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipDeviceGetAttribute"));
-    // The m = 3 fused FP64 half step runs on the matrix cores unless
-    // HERMITE_FUSED_KERNEL=valu asks for the vector kernel (comparison runs).
-    const char* kern = std::getenv("HERMITE_FUSED_KERNEL");
     ctx->precision = o.precision;
-    ctx->use_mfma = (m == 3) && o.fused && !(kern && std::strcmp(kern, "valu") == 0);
+    ctx->m3_kernel = (o.kernel == HERMITE_KERNEL_VALU) ? 0 : 1;
     std::vector<unsigned char> Kdev;
     if (o.precision != HERMITE_PREC_FP64) {
         Kdev.resize(hermite::mixed_operator_bytes(o.precision));
         hermite::mixed_build_operators(o.precision, K.data(), Kdev.data());
-    } else if (ctx->use_mfma) {
+    } else if (m == 3 && o.fused && ctx->m3_kernel == 1) {
         Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
         hermite::mfma_permute_operators(K.data(), (double*)Kdev.data());
+    } else if (m == 3 && o.fused) {
+        Kdev.resize(hermite::valu4_operator_doubles() * sizeof(double));
+        hermite::valu4_build_operators(K.data(), (double*)Kdev.data());
     } else {
         const std::vector<double> Kc = hermite::fused_operators_by_column(m, K);
         Kdev.resize(Kc.size() * sizeof(double));

@@ -1,0 +1,124 @@
+// Fused Hermite half step for m = 3 in FP64 on the vector ALUs.
+//
+// One lane per cell and output field. Per parity class p the half step is
+// the dense map y_p = K_p x_p (16 new values x 128 class inputs, the class
+// inputs being the 2x2x2 butterflies of the corner data); a lane computes the
+// 8 new values of its field for all 8 classes (64 accumulators). The operator
+// entries are wave-uniform, so they come from scalar loads and enter the FMAs
+// as scalar operands. Each input column is loaded as 8 corner values per lane
+// (64 consecutive cells per load instruction, one column, contiguous), formed
+// into its 8 butterfly outputs once and used by all 8 classes.
+//
+// Column order: 16 rounds; round r takes, for each parity pattern of d, the
+// r-th column of that pattern in order of decreasing |d| (field v before u),
+// so the small high-order inputs are summed first.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fused_common.h"
+#include "kernels.h"
+
+namespace hermite {
+namespace {
+
+using fused::butterfly8;
+using fused::Cell16;
+using fused::cell_nodes;
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void load_col(const double* __restrict__ src, size_t pitch, const Cell16& c, int col,
+                                         double* v) {
+    const double* __restrict__ b = src + (size_t)col * pitch;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = b[c.corner[s]];
+}
+
+struct RoundTable {
+    int col[16][8];  // col[r][dpar]
+    constexpr RoundTable() : col() {
+        int cnt[8] = {};
+        for (int s = 9; s >= 0; --s)
+            for (int f = 1; f >= 0; --f)
+                for (int d3 = 0; d3 < 4; ++d3)
+                    for (int d2 = 0; d2 < 4; ++d2) {
+                        const int d1 = s - d3 - d2;
+                        if (d1 < 0 || d1 > 3) continue;
+                        const int par = (d1 & 1) | ((d2 & 1) << 1) | ((d3 & 1) << 2);
+                        col[cnt[par]++][par] = f * 64 + (d3 * 4 + d2) * 4 + d1;
+                    }
+    }
+};
+__constant__ RoundTable kRounds = RoundTable();
+
+__global__ __launch_bounds__(kThreads) void fused_valu4_kernel(const double* __restrict__ src,
+                                                               double* __restrict__ dst,
+                                                               const double* __restrict__ Kv, uint32_t n,
+                                                               size_t pitch, uint32_t off) {
+    const uint32_t ncell = n * n * n;
+    const uint32_t fo = blockIdx.x & 1;
+    const uint32_t cell = (blockIdx.x >> 1) * kThreads + threadIdx.x;
+    const bool valid = cell < ncell;
+    const Cell16 c = cell_nodes(valid ? cell : 0u, n, off);
+    const double* __restrict__ Kf = Kv + (size_t)fo * (128 * 64);
+    double acc[8][8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc[p][r] = 0.0;
+    for (int rd = 0; rd < 16; ++rd) {
+#pragma unroll
+        for (int dp = 0; dp < 8; ++dp) {
+            double v[8];
+            load_col(src, pitch, c, kRounds.col[rd][dp], v);
+            double T[8];
+            butterfly8(v, T);
+            const double* __restrict__ kk = Kf + (rd * 8 + dp) * 64;  // [class][row]
+            // class p takes the butterfly output p xor (d mod 2)
+#pragma unroll
+            for (int p = 0; p < 8; ++p)
+#pragma unroll
+                for (int r = 0; r < 8; ++r) acc[p][r] = __builtin_fma(kk[p * 8 + r], T[p ^ dp], acc[p][r]);
+        }
+    }
+    if (!valid) return;
+    // row r = (o3, o2, o1) of class p: derivative orders j = p + 2 o
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int j1 = p1 + 2 * (r & 1), j2 = p2 + 2 * ((r >> 1) & 1), j3 = p3 + 2 * (r >> 2);
+            dst[(size_t)(fo * 64 + (j3 * 4 + j2) * 4 + j1) * pitch + c.out] = acc[p][r];
+        }
+    }
+}
+
+}  // namespace
+
+size_t valu4_operator_doubles() { return (size_t)2 * 128 * 64; }
+
+void valu4_build_operators(const double* K, double* Kv) {
+    // K: [8][16][128] canonical class operators (rows (fo, o3, o2, o1), columns
+    // f*64 + dd). Kv[fo][round][dpar][class][row] with row = (o3, o2, o1).
+    constexpr RoundTable R{};
+    for (int fo = 0; fo < 2; ++fo)
+        for (int rd = 0; rd < 16; ++rd)
+            for (int dp = 0; dp < 8; ++dp)
+                for (int p = 0; p < 8; ++p)
+                    for (int r = 0; r < 8; ++r)
+                        Kv[((((size_t)fo * 16 + rd) * 8 + dp) * 8 + p) * 8 + r] =
+                            K[((size_t)p * 16 + fo * 8 + r) * 128 + R.col[rd][dp]];
+}
+
+hipError_t launch_fused_valu4(const double* src, double* dst, const double* Kv, int n, size_t pitch, int off,
+                              hipStream_t st) {
+    const uint32_t ncell = (uint32_t)n * n * n;
+    const uint32_t blocks = 2 * ((ncell + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(fused_valu4_kernel, dim3(blocks), dim3(kThreads), 0, st, src, dst, Kv, (uint32_t)n, pitch,
+                       (uint32_t)off);
+    return hipGetLastError();
+}
+
+}  // namespace hermite

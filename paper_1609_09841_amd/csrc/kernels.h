@@ -29,6 +29,14 @@ hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm
 void mfma_permute_operators(const double* K, double* Kperm);
 size_t mfma_operator_doubles();
 
+// Same fused FP64 half step for m = 3 on the vector ALUs: one lane per cell
+// and output field, operator entries as scalar operands. Kv:
+// valu4_build_operators output (valu4_operator_doubles() doubles).
+hipError_t launch_fused_valu4(const double* src, double* dst, const double* Kv, int n, size_t pitch, int off,
+                              hipStream_t st);
+size_t valu4_operator_doubles();
+void valu4_build_operators(const double* K, double* Kv);
+
 // Mixed-precision fused half step (m = 3): precision 1 = FP32 matrix cores,
 // 2 = split BF16 (three products), both with FP32 accumulation; FP64 state,
 // FP64 corner-mean part and FP64 update. Aops: mixed_build_operators output

@@ -36,7 +36,7 @@ def test_options_struct_matches_header_field_order():
 
 def test_default_options():
     o = B.hermite_default_options()
-    assert (o.precision, o.evolution, o.rk_substeps, o.q, o.fused, o.poison) == (0, 0, 1, 0, 1, 0)
+    assert (o.precision, o.evolution, o.rk_substeps, o.q, o.fused, o.poison, o.kernel) == (0, 0, 1, 0, 1, 0, 0)
     assert not o.stream
 
 
@@ -61,7 +61,7 @@ def test_create_rejects_bad_arguments(args, what):
 
 @pytest.mark.parametrize("field,value", [
     ("precision", 3), ("precision", -1), ("evolution", 2), ("rk_substeps", -1), ("rk_substeps", 65),
-    ("q", -1), ("q", 65), ("fused", 2), ("poison", 5),
+    ("q", -1), ("q", 65), ("fused", 2), ("poison", 5), ("kernel", -1), ("kernel", 3),
 ])
 def test_create_rejects_bad_options(field, value):
     o = B.hermite_default_options()

@@ -268,3 +268,25 @@ def test_full_size_128_m3_sampled(fused, evolution):
 def test_max_size_256_m3_sampled():
     """256^3 cells, m = 3: 2 x 17.2 GB of state, 1 full step, fused."""
     _assert_sampled(*_sampled_check(256, 3, 1, True, "taylor", nsamples=8))
+
+
+@pytest.mark.parametrize("evolution", ["taylor", "rk4"])
+@pytest.mark.parametrize("n", [3, 7, 16])
+def test_m3_vector_kernel_against_oracle_and_matrix_kernel(n, evolution):
+    """The m = 3 fused half step on the vector ALUs (kernel="valu") computes
+    the same contraction as the matrix-core kernel with another summation
+    order: both must meet the oracle bound, and agree with each other."""
+    u0, ut0 = I.fourier_exact(n, 3, I.fourier_modes(kmax=1), t=0.05)
+    u0, ut0 = u0.numpy(), ut0.numpy()
+    steps = 3
+    vu, vv, _ = gpu_run(n, 3, u0, ut0, steps, fused=True, evolution=evolution, kernel="valu")
+    mu, mv, _ = gpu_run(n, 3, u0, ut0, steps, fused=True, evolution=evolution, kernel="mfma")
+    ou, ov = O.run(n, 3, 0.5, 1.0, u0, ut0, steps, evolution)
+    lu, lv = O.run(n, 3, 0.5, 1.0, u0, ut0, steps, evolution, ld=True)
+    fu, fv = rel(ou, lu), rel(ov, lv)
+    print(f"  valu-oracle u {rel(vu, ou):.2e} ut {rel(vv, ov):.2e}; valu-mfma u {rel(vu, mu):.2e} "
+          f"ut {rel(vv, mv):.2e}; oracle floor u {fu:.2e} ut {fv:.2e}", flush=True)
+    for g_u, g_v in ((vu, vv), (mu, mv)):
+        assert rel(g_u, ou) <= max(TOL, 3 * fu) and rel(g_v, ov) <= max(TOL, 3 * fv)
+        assert rel(g_u, lu) <= max(TOL, 1.5 * fu) and rel(g_v, lv) <= max(TOL, 1.5 * fv)
+    assert rel(vu, mu) <= max(TOL, 3 * fu) and rel(vv, mv) <= max(TOL, 3 * fv)
