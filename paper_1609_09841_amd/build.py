@@ -39,5 +39,22 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_microbench(verbose: bool = False) -> str:
+    """The instruction-throughput microbenchmark (microbench/mfma_rate.hip)."""
+    src = os.path.join(HERE, "microbench", "mfma_rate.hip")
+    exe = os.path.join(HERE, "microbench", "mfma_rate")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-result", "-Wno-unused-value", "-o", exe + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"hipcc failed ({res.returncode})")
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_microbench(verbose=True))
