@@ -106,7 +106,8 @@ int half_step(hermite_ctx* ctx, int from) {
         } else if (ctx->m == 3) {
             e = hermite::launch_fused_valu4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         } else {
-            e = hermite::launch_fused(ctx->m, src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
+            e = hermite::launch_fused_valu_small(ctx->m, src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off,
+                                                 ctx->stream);
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "fused half-step launch");
     } else {
@@ -223,13 +224,12 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     } else if (m == 3 && o.fused && ctx->m3_kernel == 1) {
         Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
         hermite::mfma_permute_operators(K.data(), (double*)Kdev.data());
-    } else if (m == 3 && o.fused) {
+    } else if (m == 3) {
         Kdev.resize(hermite::valu4_operator_doubles() * sizeof(double));
         hermite::valu4_build_operators(K.data(), (double*)Kdev.data());
     } else {
-        const std::vector<double> Kc = hermite::fused_operators_by_column(m, K);
-        Kdev.resize(Kc.size() * sizeof(double));
-        std::memcpy(Kdev.data(), Kc.data(), Kdev.size());
+        Kdev.resize(hermite::valu_small_operator_doubles(m) * sizeof(double));
+        hermite::valu_small_build_operators(m, K.data(), (double*)Kdev.data());
     }
     e = hipMalloc(&ctx->K, Kdev.size());
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));

@@ -165,30 +165,4 @@ std::vector<double> fused_class_operators(int m, double lam, const std::vector<d
     return K;
 }
 
-std::vector<int> accumulation_order(int m) {
-    const int M = m + 1, M3 = M * M * M;
-    std::vector<int> order;
-    order.reserve(2 * M3);
-    for (int s = 3 * m; s >= 0; --s)
-        for (int f = 1; f >= 0; --f)
-            for (int d3 = 0; d3 < M; ++d3)
-                for (int d2 = 0; d2 < M; ++d2) {
-                    const int d1 = s - d3 - d2;
-                    if (d1 < 0 || d1 >= M) continue;
-                    order.push_back(f * M3 + (d3 * M + d2) * M + d1);
-                }
-    return order;
-}
-
-std::vector<double> fused_operators_by_column(int m, const std::vector<double>& K) {
-    const int M = m + 1, NC = 2 * M * M * M, RM = rows_max(m);
-    const std::vector<int> order = accumulation_order(m);
-    std::vector<double> out(K.size(), 0.0);
-    for (int pc = 0; pc < 8; ++pc)
-        for (int ci = 0; ci < NC; ++ci)
-            for (int r = 0; r < RM; ++r)
-                out[((size_t)pc * NC + ci) * RM + r] = K[((size_t)pc * RM + r) * NC + order[(size_t)ci]];
-    return out;
-}
-
 }  // namespace hermite

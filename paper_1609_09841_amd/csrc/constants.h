@@ -36,14 +36,6 @@ std::vector<double> evolution_poly(int m, int evolution, int q, int rk_substeps)
 // Layout [8][rows_max][2*M^3], rows_max = 2*nout(p=0)^3, unused rows zero.
 std::vector<double> fused_class_operators(int m, double lam, const std::vector<double>& cpoly);
 
-// Columns in accumulation order: derivative order |d| from 3m down to 0, field
-// v before u, then (d3, d2) ascending. Small (high-order) inputs come first.
-std::vector<int> accumulation_order(int m);
-
-// K re-laid out as [8][2*M^3 in accumulation order][rows_max]: the rows of one
-// column are contiguous, which is the order the fused VALU kernel reads.
-std::vector<double> fused_operators_by_column(int m, const std::vector<double>& K);
-
 int rows_max(int m);
 int nout(int M, int p);
 

@@ -1,4 +1,5 @@
-// Fused Hermite half step for m = 3 in FP64 on the vector ALUs.
+// Fused Hermite half steps in FP64 on the vector ALUs: the m = 3 variant of
+// the matrix-core kernel, and the m = 1, 2 kernels.
 //
 // One lane per cell and output field. Per parity class p the half step is
 // the dense map y_p = K_p x_p (16 new values x 128 class inputs, the class
@@ -95,7 +96,123 @@ __global__ __launch_bounds__(kThreads) void fused_valu4_kernel(const double* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// m = 1, 2: one lane per cell computes all 2 M^3 new values. Columns (all
+// 2 M^3 input columns, small |d| last) are fully unrolled, so the parity
+// pattern of each column and the class each accumulator belongs to are
+// compile-time constants; the operator is dense per column over all classes'
+// outputs (the class inputs differ per class: butterfly output p xor par(d)).
+// ---------------------------------------------------------------------------
+template <int M>
+struct SmallLayout {
+    static constexpr int M3 = M * M * M, NC = 2 * M3, NO = 2 * M3;
+    int col[NC];          // columns in accumulation order
+    int out_class[NO];    // class of output slot o
+    int out_j[NO];        // destination row fo * M3 + (j3 M + j2) M + j1 of slot o
+    int out_row[NO];      // row of slot o in its class operator (canonical order)
+    constexpr SmallLayout() : col(), out_class(), out_j(), out_row() {
+        int k = 0;
+        for (int s = 3 * (M - 1); s >= 0; --s)
+            for (int f = 1; f >= 0; --f)
+                for (int d3 = 0; d3 < M; ++d3)
+                    for (int d2 = 0; d2 < M; ++d2) {
+                        const int d1 = s - d3 - d2;
+                        if (d1 < 0 || d1 >= M) continue;
+                        col[k++] = f * M3 + (d3 * M + d2) * M + d1;
+                    }
+        int o = 0;
+        for (int p = 0; p < 8; ++p) {
+            const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
+            const int n1 = (M + 1 - p1) / 2, n2 = (M + 1 - p2) / 2, n3 = (M + 1 - p3) / 2, nof = n1 * n2 * n3;
+            for (int fo = 0; fo < 2; ++fo)
+                for (int o3 = 0; o3 < n3; ++o3)
+                    for (int o2 = 0; o2 < n2; ++o2)
+                        for (int o1 = 0; o1 < n1; ++o1) {
+                            out_class[o] = p;
+                            out_row[o] = fo * nof + (o3 * n2 + o2) * n1 + o1;
+                            const int j1 = p1 + 2 * o1, j2 = p2 + 2 * o2, j3 = p3 + 2 * o3;
+                            out_j[o] = fo * M3 + (j3 * M + j2) * M + j1;
+                            ++o;
+                        }
+        }
+    }
+    static constexpr int parity(int c) {
+        const int dd = c % M3;
+        const int d1 = dd % M, d2 = (dd / M) % M, d3 = dd / (M * M);
+        return (d1 & 1) | ((d2 & 1) << 1) | ((d3 & 1) << 2);
+    }
+};
+
+template <int M, int C>
+struct SmallCols {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t pitch, const Cell16& cc,
+                                               const double* __restrict__ Kv, double* acc) {
+        constexpr SmallLayout<M> L{};
+        constexpr int NO = SmallLayout<M>::NO;
+        constexpr int col = L.col[C], par = SmallLayout<M>::parity(col);
+        double v[8];
+        load_col(src, pitch, cc, col, v);
+        double T[8];
+        butterfly8(v, T);
+        const double* __restrict__ kk = Kv + C * NO;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o] = __builtin_fma(kk[o], T[L.out_class[o] ^ par], acc[o]);
+        if constexpr (C + 1 < SmallLayout<M>::NC) SmallCols<M, C + 1>::run(src, pitch, cc, Kv, acc);
+    }
+};
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void fused_valu_small_kernel(const double* __restrict__ src,
+                                                                    double* __restrict__ dst,
+                                                                    const double* __restrict__ Kv, uint32_t n,
+                                                                    size_t pitch, uint32_t off) {
+    constexpr SmallLayout<M> L{};
+    constexpr int NO = SmallLayout<M>::NO;
+    const uint32_t ncell = n * n * n;
+    const uint32_t cell = blockIdx.x * kThreads + threadIdx.x;
+    if (cell >= ncell) return;
+    const Cell16 c = cell_nodes(cell, n, off);
+    double acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+    SmallCols<M, 0>::run(src, pitch, c, Kv, acc);
+#pragma unroll
+    for (int o = 0; o < NO; ++o) dst[(size_t)L.out_j[o] * pitch + c.out] = acc[o];
+}
+
+template <int M>
+void small_build(const double* K, double* Kv) {
+    constexpr SmallLayout<M> L{};
+    constexpr int NO = SmallLayout<M>::NO, NC = SmallLayout<M>::NC;
+    const int no0 = (M + 1) / 2, RM = 2 * no0 * no0 * no0;
+    for (int c = 0; c < NC; ++c)
+        for (int o = 0; o < NO; ++o)
+            Kv[(size_t)c * NO + o] = K[((size_t)L.out_class[o] * RM + L.out_row[o]) * NC + L.col[c]];
+}
+
 }  // namespace
+
+size_t valu_small_operator_doubles(int m) { return (size_t)(2 * (m + 1) * (m + 1) * (m + 1)) * (2 * (m + 1) * (m + 1) * (m + 1)); }
+
+void valu_small_build_operators(int m, const double* K, double* Kv) {
+    if (m == 1) small_build<2>(K, Kv);
+    if (m == 2) small_build<3>(K, Kv);
+}
+
+hipError_t launch_fused_valu_small(int m, const double* src, double* dst, const double* Kv, int n, size_t pitch,
+                                   int off, hipStream_t st) {
+    const uint32_t ncell = (uint32_t)n * n * n;
+    const dim3 grid((ncell + kThreads - 1) / kThreads), block(kThreads);
+    if (m == 1)
+        hipLaunchKernelGGL(fused_valu_small_kernel<2>, grid, block, 0, st, src, dst, Kv, (uint32_t)n, pitch,
+                           (uint32_t)off);
+    else if (m == 2)
+        hipLaunchKernelGGL(fused_valu_small_kernel<3>, grid, block, 0, st, src, dst, Kv, (uint32_t)n, pitch,
+                           (uint32_t)off);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 size_t valu4_operator_doubles() { return (size_t)2 * 128 * 64; }
 

@@ -13,15 +13,13 @@ namespace hermite {
 // column node (i,j,k) sits at (k n + j) n + i. pitch >= n^3 is padded so that
 // the columns of one node do not all fall into the same cache set.
 //
-// One fused half step (interpolation + evolution + truncation per cell) with
-// the per-parity-class operators K ([8][rows_max][2 M^3], FP64). src/dst are
-// two-field grids; the cell with lower corner (i,j,k) of src
-// writes node (i+off, j+off, k+off) mod n of dst (off = 0 primal->dual,
-// off = 1 dual->primal).
-hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, size_t pitch, int off,
-                        hipStream_t st);
-
-// Same fused half step on the FP64 matrix cores (m = 3 only). Kperm: the
+// Fused half step (interpolation + evolution + truncation per cell) with the
+// per-parity-class operators K of constants.h ([8][rows_max][2 M^3], FP64),
+// laid out for the kernel in use: src/dst are two-field grids; the cell with
+// lower corner (i,j,k) of src writes node (i+off, j+off, k+off) mod n of dst
+// (off = 0 primal->dual, off = 1 dual->primal).
+//
+// m = 3 on the FP64 matrix cores. Kperm: the
 // class operators permuted by mfma_permute_operators (mfma_operator_doubles()
 // doubles). grid: workgroups, a multiple of 8 (one per CU is enough).
 hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, size_t pitch, int off,
@@ -36,6 +34,14 @@ hipError_t launch_fused_valu4(const double* src, double* dst, const double* Kv, 
                               hipStream_t st);
 size_t valu4_operator_doubles();
 void valu4_build_operators(const double* K, double* Kv);
+
+// Fused FP64 half step for m = 1, 2 on the vector ALUs: one lane per cell,
+// all 2 (m+1)^3 new values. Kv: valu_small_build_operators output
+// (valu_small_operator_doubles(m) doubles).
+hipError_t launch_fused_valu_small(int m, const double* src, double* dst, const double* Kv, int n, size_t pitch,
+                                   int off, hipStream_t st);
+size_t valu_small_operator_doubles(int m);
+void valu_small_build_operators(int m, const double* K, double* Kv);
 
 // Mixed-precision fused half step (m = 3): precision 1 = FP32 matrix cores,
 // 2 = split BF16 (three products), both with FP32 accumulation; FP64 state,

@@ -1,4 +1,5 @@
-// Hermite half-step kernels for gfx950 (CDNA4), FP64 vector path.
+// Hermite half-step kernels for gfx950 (CDNA4): the two-kernel variant
+// (interpolation, then evolution, Sec. 3.1-3.2) and the state scaling.
 //
 // Cell data flow (Sec. 2, Eq. 3; Sec. 3.1-3.2): gather the 8 vertices of a
 // cell, interpolate (tensor Hermite, degree 2m+1 per axis), evolve through the
@@ -64,62 +65,9 @@ __device__ __forceinline__ double class_input(const double* __restrict__ b, cons
 __device__ __forceinline__ double parity_sign(int p, int d) { return ((p + d) & 1) ? -1.0 : 1.0; }
 
 // ---------------------------------------------------------------------------
-// Fused half step, one thread per (cell, parity class); the class comes from
-// blockIdx.y, so the class operator is wave-uniform (scalar loads).
-// Columns run from the highest derivative order |d| = 3m down to 0, field v
-// before u, flat index ascending: the order the host lays K out in.
-// ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(256) void fused_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                                    const double* __restrict__ K, uint32_t n, size_t pitch,
-                                                    uint32_t off) {
-    constexpr int M3 = M * M * M, NC = 2 * M3;
-    constexpr int RM = 2 * nout_c(M, 0) * nout_c(M, 0) * nout_c(M, 0);
-    const uint32_t ncell = n * n * n;
-    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
-    if (cell >= ncell) return;
-    const CellIdx c = cell_index(cell, n, off);
-    const size_t plane = pitch;
-    const int pc = blockIdx.y;
-    const int p1 = pc & 1, p2 = (pc >> 1) & 1, p3 = pc >> 2;
-    const int no1 = nout_c(M, p1), no2 = nout_c(M, p2), no3 = nout_c(M, p3);
-    const int nof = no1 * no2 * no3, nr = 2 * nof;
-    const double* __restrict__ Kc = K + (size_t)pc * RM * NC;
-    double acc[RM];
-#pragma unroll
-    for (int r = 0; r < RM; ++r) acc[r] = 0.0;
-    int ci = 0;
-    for (int s = 3 * (M - 1); s >= 0; --s)
-        for (int f = 1; f >= 0; --f)
-            for (int d3 = 0; d3 < M; ++d3)
-                for (int d2 = 0; d2 < M; ++d2) {
-                    const int d1 = s - d3 - d2;
-                    if (d1 < 0 || d1 >= M) continue;
-                    const int col = f * M3 + (d3 * M + d2) * M + d1;
-                    const double x = class_input(src + (size_t)col * plane, c, parity_sign(p1, d1),
-                                                 parity_sign(p2, d2), parity_sign(p3, d3));
-                    const double* __restrict__ kr = Kc + (size_t)ci * RM;
-#pragma unroll
-                    for (int r = 0; r < RM; ++r)
-                        if (r < nr) acc[r] = __builtin_fma(kr[r], x, acc[r]);
-                    ++ci;
-                }
-    for (int fo = 0; fo < 2; ++fo)
-        for (int o3 = 0; o3 < no3; ++o3)
-            for (int o2 = 0; o2 < no2; ++o2)
-                for (int o1 = 0; o1 < no1; ++o1) {
-                    const int r = fo * nof + (o3 * no2 + o2) * no1 + o1;
-                    const int j1 = p1 + 2 * o1, j2 = p2 + 2 * o2, j3 = p3 + 2 * o3;
-                    double val = 0.0;
-#pragma unroll
-                    for (int rr = 0; rr < RM; ++rr)
-                        if (rr == r) val = acc[rr];
-                    dst[(size_t)(fo * M3 + (j3 * M + j2) * M + j1) * plane + c.out] = val;
-                }
-}
-
-// ---------------------------------------------------------------------------
-// Two-kernel variant, interpolation: one thread per (cell, class, field).
+// Two-kernel variant, interpolation: one thread per (cell, class, field);
+// (field, class) is the fastest-varying part of the block index, so the 16
+// blocks reading the same cells' corners run together.
 // Applies the parity blocks of H along x1, x2, x3 (Alg. 2 restricted to one
 // class) and writes the monomial coefficients R[f][k3][k2][k1][cell].
 // ---------------------------------------------------------------------------
@@ -128,10 +76,10 @@ __global__ __launch_bounds__(256) void interp_kernel(const double* __restrict__ 
                                                      const double* __restrict__ Hp, uint32_t n, size_t pitch) {
     constexpr int M3 = M * M * M, P = 2 * M, P3 = P * P * P;
     const uint32_t ncell = n * n * n;
-    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t cell = (blockIdx.x >> 4) * 256u + threadIdx.x;
     if (cell >= ncell) return;
     const CellIdx c = cell_index(cell, n, 0);
-    const int f = blockIdx.y & 1, pc = blockIdx.y >> 1;
+    const int f = blockIdx.x & 1, pc = (blockIdx.x >> 1) & 7;
     const int p1 = pc & 1, p2 = (pc >> 1) & 1, p3 = pc >> 2;
     const double* __restrict__ H1 = Hp + p1 * M * M;
     const double* __restrict__ H2 = Hp + p2 * M * M;
@@ -232,11 +180,11 @@ __global__ __launch_bounds__(256) void evolve_kernel(const double* __restrict__ 
     constexpr int S2 = M * M, M3 = M * M * M, P = 2 * M, P3 = P * P * P;
     const uint32_t ncell = n * n * n;
     const int i3 = threadIdx.x % G;
-    const uint32_t cell = blockIdx.x * SLOTS + threadIdx.x / G;
+    const uint32_t cell = (blockIdx.x >> 3) * SLOTS + threadIdx.x / G;
     const bool valid = cell < ncell;
     const uint32_t cc = valid ? cell : 0u;
     const CellIdx c = cell_index(cc, n, off);
-    const int pc = blockIdx.y;
+    const int pc = blockIdx.x & 7;
     const int p1 = pc & 1, p2 = (pc >> 1) & 1, p3 = pc >> 2;
     const int k3 = p3 + 2 * i3;
     const bool live = valid && (i3 < M);
@@ -321,23 +269,9 @@ __global__ void scale_kernel(double* __restrict__ dst, size_t dpitch, const doub
 
 }  // namespace
 
-hipError_t launch_fused(int m, const double* src, double* dst, const double* K, int n, size_t pitch, int off,
-                        hipStream_t st) {
-    const uint32_t ncell = (uint32_t)n * n * n;
-    const dim3 grid((ncell + 255) / 256, 8), block(256);
-    const uint32_t un = (uint32_t)n, uo = (uint32_t)off;
-    switch (m) {
-        case 1: hipLaunchKernelGGL(fused_kernel<2>, grid, block, 0, st, src, dst, K, un, pitch, uo); break;
-        case 2: hipLaunchKernelGGL(fused_kernel<3>, grid, block, 0, st, src, dst, K, un, pitch, uo); break;
-        case 3: hipLaunchKernelGGL(fused_kernel<4>, grid, block, 0, st, src, dst, K, un, pitch, uo); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch, hipStream_t st) {
     const uint32_t ncell = (uint32_t)n * n * n;
-    const dim3 grid((ncell + 255) / 256, 16), block(256);
+    const dim3 grid(16 * ((ncell + 255) / 256)), block(256);
     const uint32_t un = (uint32_t)n;
     switch (m) {
         case 1: hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, st, src, R, Hp, un, pitch); break;
@@ -353,7 +287,7 @@ hipError_t launch_evolve(int m, const double* R, double* dst, int n, size_t pitc
     const uint32_t ncell = (uint32_t)n * n * n;
     const int G = (m + 1 <= 2) ? 2 : 4;
     const uint32_t slots = 256 / G;
-    const dim3 grid((ncell + slots - 1) / slots, 8), block(256);
+    const dim3 grid(8 * ((ncell + slots - 1) / slots)), block(256);
     switch (m) {
         case 1: hipLaunchKernelGGL(evolve_kernel<2>, grid, block, 0, st, R, dst, (uint32_t)n, pitch, (uint32_t)off, evolution, q, S, lam); break;
         case 2: hipLaunchKernelGGL(evolve_kernel<3>, grid, block, 0, st, R, dst, (uint32_t)n, pitch, (uint32_t)off, evolution, q, S, lam); break;
