@@ -33,6 +33,12 @@
  *     cell with lower corner (i, j, k) writes primal node (i+1, j+1, k+1).
  *   - "Multi-stage" evolution is classical 4-stage Runge-Kutta on the cell
  *     ODE dW/dsigma = L W, with S substeps per half step.
+ *   - Point source (an extension: the paper evolves homogeneous problems):
+ *     the forcing f = amp g(x) w(t) enters the vt equation as (tau h/c) f;
+ *     its space and time Taylor coefficients about the cell centre and the
+ *     half step's start join the series recursion. The spatial factor is a
+ *     product of 1D Gaussians at the periodic nearest image, each cut to 0
+ *     beyond 6 sigma; the wavelet is a Ricker wavelet.
  *
  * Array layout of a grid field: [d3][d2][d1][k][j][i], i (x1) fastest, the
  * tensor u[m3][m2][m1][n3][n2][n1] of Sec. 3.1. A two-field state is
@@ -453,4 +459,171 @@ int oracle_point(int n, int m, real cfl, real c, int evo, int param, int nsteps,
     free(ub);
     free(vb);
     return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Forced wave equation u_tt = c^2 Lap u + f, f(x, t) = amp g(x) w(t), with g a
+ * unit-mass Gaussian of standard deviation sigma around a source point and w
+ * a Ricker wavelet (1 - 2 beta s^2) exp(-beta s^2), s = t - t0,
+ * beta = (pi f0)^2. (Extension of Sec. 2: the Taylor series of the cell
+ * solution now also carries the forcing.) For tests, sigma <= 0 stands for a
+ * spatially uniform g = 1.
+ * ------------------------------------------------------------------------ */
+
+/* Taylor coefficients e_k, k < K, of exp(p0 + p1 t + p2 t^2) about t = 0,
+ * from (k+1) e_{k+1} = p1 e_k + 2 p2 e_{k-1} (the derivative of the
+ * exponent times the series). */
+static void or_exp_quadratic_series(real p0, real p1, real p2, int K, real *e)
+{
+    e[0] = exp(p0);
+    for (int k = 0; k + 1 < K; ++k) {
+        real v = p1 * e[k];
+        if (k >= 1) v += 2.0 * p2 * e[k - 1];
+        e[k + 1] = v / (real)(k + 1);
+    }
+}
+
+/* Scaled Taylor coefficients h^a/a! g1^(a) of the 1D Gaussian factor
+ * g1(x) = exp(-(x - s)^2 / (2 sigma^2)) / (sigma sqrt(2 pi)) at the point
+ * whose nearest-image offset from s is d: the Taylor series of
+ * g1(x_c + h xi) in xi. Zero beyond 6 sigma. */
+int oracle_gauss_taylor(real d, real sigma, real h, int K, real *g)
+{
+    if (K < 1 || K > 64) return -1;
+    if (sigma <= 0.0) {
+        for (int a = 0; a < K; ++a) g[a] = (a == 0) ? 1.0 : 0.0;
+        return 0;
+    }
+    if (fabs(d) > 6.0 * sigma) {
+        for (int a = 0; a < K; ++a) g[a] = 0.0;
+        return 0;
+    }
+    const real s2 = 2.0 * sigma * sigma;
+    or_exp_quadratic_series(-d * d / s2, -2.0 * d * h / s2, -h * h / s2, K, g);
+    const real norm = 1.0 / (sigma * sqrt(2.0 * 3.14159265358979323846264338327950288L));
+    for (int a = 0; a < K; ++a) g[a] *= norm;
+    return 0;
+}
+
+/* Time Taylor coefficients w_k = tau^k/k! w^(k)(ta) of the Ricker wavelet,
+ * k < K: the series of (1 + 2 phi(sig)) exp(phi(sig)) with
+ * phi(sig) = -beta (ta - t0 + tau sig)^2. */
+int oracle_ricker_taylor(real ta, real tau, real f0, real t0, int K, real *w)
+{
+    if (K < 1 || K > 64) return -1;
+    const real pi = 3.14159265358979323846264338327950288L;
+    const real beta = pi * pi * f0 * f0, s = ta - t0;
+    const real p0 = -beta * s * s, p1 = -2.0 * beta * s * tau, p2 = -beta * tau * tau;
+    real e[66];
+    or_exp_quadratic_series(p0, p1, p2, K, e);
+    for (int k = 0; k < K; ++k) {
+        real v = (1.0 + 2.0 * p0) * e[k];
+        if (k >= 1) v += 2.0 * p1 * e[k - 1];
+        if (k >= 2) v += 2.0 * p2 * e[k - 2];
+        w[k] = v;
+    }
+    return 0;
+}
+
+/*
+ * Forced Taylor evolution of one cell over the half step, by the forward
+ * recursion of the series: W_0 = (Ru, Rv) and for s = 1..q
+ *   W_s = (L W_{s-1} + (0, wk[s-1] G)) / s,
+ * with L(a, b) = lam (b, Lap a); the result sum_{s<=q} W_s overwrites Ru, Rv.
+ * G[j3][j2][j1] is the forcing polynomial of the cell in xi, already scaled
+ * to the vt equation; wk holds q time coefficients.
+ */
+void oracle_evolve_taylor_forced(int m, int q, real lam, real *Ru, real *Rv, const real *G, const real *wk)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    real wu[OR_MAXP * OR_MAXP * OR_MAXP], wv[OR_MAXP * OR_MAXP * OR_MAXP];
+    real lu[OR_MAXP * OR_MAXP * OR_MAXP], lv[OR_MAXP * OR_MAXP * OR_MAXP];
+    memcpy(wu, Ru, sizeof(real) * n3);
+    memcpy(wv, Rv, sizeof(real) * n3);
+    for (int s = 1; s <= q; ++s) {
+        or_apply_L(m, lam, wu, wv, lu, lv);
+        for (int t = 0; t < n3; ++t) {
+            wu[t] = lu[t] / (real)s;
+            wv[t] = (lv[t] + wk[s - 1] * G[t]) / (real)s;
+            Ru[t] += wu[t];
+            Rv[t] += wv[t];
+        }
+    }
+}
+
+/* One forced half step (as oracle_half_step, Taylor with q stages), the half
+ * step starting at time ta. Cell centres: (i + 1/2) h on the primal grid's
+ * cells (to_dual = 1), (i + 1) h on the dual grid's (to_dual = 0). */
+static void or_half_step_forced(int n, int m, const real *H, real lam, int q, const real *src, real *dst,
+                                int to_dual, real h, real tau, real c, real ta, const real *sx, real sigma,
+                                real f0, real t0, real amp)
+{
+    const int M = m + 1, P = 2 * M, M3 = M * M * M;
+    const long nn = (long)n * n * n;
+    const int off = to_dual ? 0 : 1;
+    real wk[64];
+    oracle_ricker_taylor(ta, tau, f0, t0, q, wk);
+    const real fscale = amp * tau * h / c;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j) {
+            real uloc[OR_MAXP * OR_MAXP * OR_MAXP], vloc[OR_MAXP * OR_MAXP * OR_MAXP];
+            real Ru[OR_MAXP * OR_MAXP * OR_MAXP], Rv[OR_MAXP * OR_MAXP * OR_MAXP];
+            real G[OR_MAXP * OR_MAXP * OR_MAXP];
+            for (int i = 0; i < n; ++i) {
+                oracle_gather_cell(n, m, src, i, j, k, uloc);
+                oracle_gather_cell(n, m, src + (long)M3 * nn, i, j, k, vloc);
+                oracle_interpolate_cell(m, H, uloc, Ru);
+                oracle_interpolate_cell(m, H, vloc, Rv);
+                const int idx[3] = {i, j, k};
+                real g1[3][OR_MAXP];
+                for (int x = 0; x < 3; ++x) {
+                    real d = ((real)idx[x] + 0.5 + (to_dual ? 0.0 : 0.5)) * h - sx[x];
+                    d -= floor(d + 0.5);
+                    oracle_gauss_taylor(d, sigma, h, P, g1[x]);
+                }
+                for (int a3 = 0; a3 < P; ++a3)
+                    for (int a2 = 0; a2 < P; ++a2)
+                        for (int a1 = 0; a1 < P; ++a1)
+                            G[(a3 * P + a2) * P + a1] = fscale * g1[0][a1] * g1[1][a2] * g1[2][a3];
+                oracle_evolve_taylor_forced(m, q, lam, Ru, Rv, G, wk);
+                const long node = ((long)((k + off) % n) * n + (j + off) % n) * n + (i + off) % n;
+                for (int d3 = 0; d3 < M; ++d3)
+                    for (int d2 = 0; d2 < M; ++d2)
+                        for (int d1 = 0; d1 < M; ++d1) {
+                            const int dd = (d3 * M + d2) * M + d1;
+                            const int jj = (d3 * P + d2) * P + d1;
+                            dst[(long)dd * nn + node] = Ru[jj];
+                            dst[(long)(M3 + dd) * nn + node] = Rv[jj];
+                        }
+            }
+        }
+}
+
+/* Forced run: as oracle_run with Taylor evolution (q stages) and the point
+ * source (sx, sigma, f0, t0, amp); the first half step starts at t = 0. */
+int oracle_run_forced(int n, int m, real cfl, real c, int q, int nsteps, real *u, real *ut, const real *sx,
+                      real sigma, real f0, real t0, real amp)
+{
+    if (n < 1 || m < 1 || m > OR_MAXM || !(cfl > 0.0) || !(c > 0.0) || nsteps < 0 || q < 1 || q > 64)
+        return -1;
+    const int M = m + 1, M3 = M * M * M;
+    const long nn = (long)n * n * n, sz = (long)M3 * nn;
+    const real h = 1.0 / (real)n;
+    const real dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    real H[OR_MAXP * OR_MAXP];
+    if (oracle_hermite_matrix(m, H) != 0) return -2;
+    real *a = (real *)malloc(sizeof(real) * 2 * sz);
+    real *b = (real *)malloc(sizeof(real) * 2 * sz);
+    if (!a || !b) { free(a); free(b); return -3; }
+    for (long t = 0; t < sz; ++t) { a[t] = u[t]; a[sz + t] = (h / c) * ut[t]; }
+    for (int s = 0; s < nsteps; ++s) {
+        const real tn = (real)s * dt;
+        or_half_step_forced(n, m, H, lam, q, a, b, 1, h, tau, c, tn, sx, sigma, f0, t0, amp);
+        or_half_step_forced(n, m, H, lam, q, b, a, 0, h, tau, c, tn + tau, sx, sigma, f0, t0, amp);
+    }
+    for (long t = 0; t < sz; ++t) { u[t] = a[t]; ut[t] = (c / h) * a[sz + t]; }
+    free(a);
+    free(b);
+    return 0;
 }

@@ -27,6 +27,7 @@ __all__ = [
     "build_oracle", "load", "exact_hermite_matrix", "hermite_matrix",
     "interpolate_cell", "laplacian", "evolve_taylor", "evolve_rk4",
     "gather_cell", "half_step", "run", "point", "point_box", "exact_q",
+    "gauss_taylor", "ricker_taylor", "evolve_taylor_forced", "run_forced",
 ]
 
 
@@ -75,6 +76,14 @@ def load(ld: bool = False):
     lib.oracle_point.restype = i
     lib.oracle_point_box.argtypes = [i, i, d, d, i, i, i, dp, dp, dp]
     lib.oracle_point_box.restype = i
+    lib.oracle_gauss_taylor.argtypes = [d, d, d, i, dp]
+    lib.oracle_gauss_taylor.restype = i
+    lib.oracle_ricker_taylor.argtypes = [d, d, d, d, i, dp]
+    lib.oracle_ricker_taylor.restype = i
+    lib.oracle_evolve_taylor_forced.argtypes = [i, i, d, dp, dp, dp, dp]
+    lib.oracle_evolve_taylor_forced.restype = None
+    lib.oracle_run_forced.argtypes = [i, i, d, d, i, i, dp, dp, dp, d, d, d, d]
+    lib.oracle_run_forced.restype = i
     if ld:
         _lib_ld = lib
     else:
@@ -259,3 +268,54 @@ def point_box(n: int, m: int, cfl: float, c: float, ubox: np.ndarray, utbox: np.
     if rc != 0:
         raise ValueError(f"oracle_point_box failed: {rc}")
     return out.astype(np.float64)
+
+
+# --- point source (forced wave equation) -----------------------------------
+
+def gauss_taylor(d: float, sigma: float, h: float, K: int) -> np.ndarray:
+    """Scaled Taylor coefficients h^a/a! g1^(a), a < K, of the unit-mass 1D
+    Gaussian factor at nearest-image offset d from the source (sigma <= 0:
+    the uniform factor 1)."""
+    out = np.zeros(K)
+    rc = load().oracle_gauss_taylor(float(d), float(sigma), float(h), int(K), _ptr(out))
+    if rc != 0:
+        raise ValueError(rc)
+    return out
+
+
+def ricker_taylor(ta: float, tau: float, f0: float, t0: float, K: int) -> np.ndarray:
+    """Time Taylor coefficients tau^k/k! w^(k)(ta), k < K, of the Ricker
+    wavelet (1 - 2 beta s^2) exp(-beta s^2), s = t - t0, beta = (pi f0)^2."""
+    out = np.zeros(K)
+    rc = load().oracle_ricker_taylor(float(ta), float(tau), float(f0), float(t0), int(K), _ptr(out))
+    if rc != 0:
+        raise ValueError(rc)
+    return out
+
+
+def evolve_taylor_forced(m: int, q: int, lam: float, Ru, Rv, G, wk):
+    """Forced Taylor evolution of one cell (forward series recursion)."""
+    P = 2 * m + 2
+    a = np.array(Ru, dtype=np.float64).reshape(P, P, P).copy()
+    b = np.array(Rv, dtype=np.float64).reshape(P, P, P).copy()
+    g = np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(P, P, P))
+    w = np.ascontiguousarray(np.asarray(wk, dtype=np.float64))
+    assert w.size >= q
+    load().oracle_evolve_taylor_forced(m, q, lam, _ptr(a), _ptr(b), _ptr(g), _ptr(w))
+    return a, b
+
+
+def run_forced(n: int, m: int, cfl: float, c: float, u, ut, nsteps: int, source: dict, q: int | None = None):
+    """As run() with Taylor evolution and the point source
+    source = {"x": (x, y, z), "sigma": s, "freq": f0, "t0": t0, "amplitude": a}."""
+    q = exact_q(m) if q is None else int(q)
+    shape = np.shape(u)
+    a = np.array(u, dtype=np.float64).ravel().copy()
+    b = np.array(ut, dtype=np.float64).ravel().copy()
+    sx = np.ascontiguousarray(np.asarray(source["x"], dtype=np.float64))
+    rc = load().oracle_run_forced(n, m, float(cfl), float(c), q, int(nsteps), _ptr(a), _ptr(b), _ptr(sx),
+                                  float(source["sigma"]), float(source["freq"]), float(source["t0"]),
+                                  float(source["amplitude"]))
+    if rc != 0:
+        raise ValueError(f"oracle_run_forced failed: {rc}")
+    return a.reshape(shape), b.reshape(shape)
