@@ -210,15 +210,23 @@ def main():
     if args.variant.startswith("fused"):
         flops = fused_flops_per_cell(m) * cells
         achieved = flops / avg_launch_s / 1e12
-        mfma = (m == 3)
-        traffic = measured_traffic() if (mfma and n == 128) else None
-        roofline = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                    "kernel": "fused_mfma_kernel (FP64 MFMA 16x16x4)" if mfma else f"fused_kernel<{m + 1}> (FP64 VALU)",
-                    "avg_launch_ms": avg_launch_s * 1e3,
-                    "algorithmic_bytes_per_launch": fused_bytes_per_cell(m) * cells,
-                    "hbm_GBps_algorithmic": fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9,
-                    "hbm_frac_algorithmic": fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9 / HBM_PEAK_GBS}
+        gbs = fused_bytes_per_cell(m) * cells / avg_launch_s / 1e9
+        common = {"avg_launch_ms": avg_launch_s * 1e3,
+                  "algorithmic_bytes_per_launch": fused_bytes_per_cell(m) * cells,
+                  "algorithmic_flops_per_launch": flops}
+        if m == 3:
+            # arithmetic intensity 14.7 flop/B, above the FP64 ridge (78.6 / 8 = 9.8)
+            traffic = measured_traffic() if n == 128 else None
+            roofline = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                        "kernel": "fused_mfma_kernel (FP64 MFMA 16x16x4)",
+                        "hbm_GBps_algorithmic": gbs, "hbm_frac_algorithmic": gbs / HBM_PEAK_GBS, **common}
+        else:
+            # m = 1, 2: 3.5 and 6.2 flop/B, below the ridge: HBM-bound
+            roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": f"fused_valu_small_kernel<{m + 1}> (FP64 VALU)",
+                        "fp64_TFLOPs": achieved, **common}
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": K, "warmup": W,

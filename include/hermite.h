@@ -138,6 +138,35 @@ int hermite_gather(hermite_ctx *ctx, double *u, double *ut, double *t_out);
 /* Stream-ordered copy of the state into device arrays (no host wait). */
 int hermite_gather_device(hermite_ctx *ctx, void *u_dev, void *ut_dev);
 
+/*
+ * Point source: the solver then advances u_tt = c^2 Lap u + f with
+ *   f(x, t) = amplitude * g(x) * w(t),
+ *   g(x) = prod_i exp(-d_i^2 / (2 sigma^2)) / (sigma sqrt(2 pi)),
+ *   w(t) = (1 - 2 beta s^2) exp(-beta s^2), s = t - t0, beta = (pi freq)^2,
+ * d_i the periodic nearest-image offset of x_i from the source point x (each
+ * factor taken as 0 beyond 6 sigma), a Gaussian in space times a Ricker
+ * wavelet in time (an extension of Sec. 2: the local Taylor series of the
+ * cell solution, Sec. 3.2, also carries the forcing; each half step adds the
+ * particular solution of the cell system with zero data to the nodes of the
+ * cells within 6 sigma of the source, after the homogeneous half step).
+ *   src: x in any real coordinates (reduced modulo 1), sigma > 0,
+ *        freq >= 0, t0 and amplitude finite; all finite. NULL (or
+ *        amplitude 0) removes the source.
+ * Needs Taylor evolution (HERMITE_EUNSUPPORTED with RK4); works with every
+ * precision and kernel (the source term itself is FP64). Takes effect with
+ * the next hermite_step; the copy is the context's, the caller keeps src.
+ * Time is the context's t = steps * dt (hermite_set_initial resets it).
+ */
+typedef struct hermite_source {
+    double x[3];      /* source point */
+    double sigma;     /* standard deviation of the Gaussian */
+    double freq;      /* peak frequency f0 of the wavelet */
+    double t0;        /* time of the wavelet's peak */
+    double amplitude; /* factor a of f */
+} hermite_source;
+
+int hermite_set_source(hermite_ctx *ctx, const hermite_source *src);
+
 /* Waits for all work enqueued on the context's stream. */
 int hermite_sync(hermite_ctx *ctx);
 

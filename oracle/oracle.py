@@ -305,17 +305,20 @@ def evolve_taylor_forced(m: int, q: int, lam: float, Ru, Rv, G, wk):
     return a, b
 
 
-def run_forced(n: int, m: int, cfl: float, c: float, u, ut, nsteps: int, source: dict, q: int | None = None):
+def run_forced(n: int, m: int, cfl: float, c: float, u, ut, nsteps: int, source: dict, q: int | None = None,
+               ld: bool = False):
     """As run() with Taylor evolution and the point source
-    source = {"x": (x, y, z), "sigma": s, "freq": f0, "t0": t0, "amplitude": a}."""
+    source = {"x": (x, y, z), "sigma": s, "freq": f0, "t0": t0, "amplitude": a}.
+    ld=True runs the long-double twin (rounding-floor measurements only)."""
     q = exact_q(m) if q is None else int(q)
     shape = np.shape(u)
-    a = np.array(u, dtype=np.float64).ravel().copy()
-    b = np.array(ut, dtype=np.float64).ravel().copy()
-    sx = np.ascontiguousarray(np.asarray(source["x"], dtype=np.float64))
-    rc = load().oracle_run_forced(n, m, float(cfl), float(c), q, int(nsteps), _ptr(a), _ptr(b), _ptr(sx),
-                                  float(source["sigma"]), float(source["freq"]), float(source["t0"]),
-                                  float(source["amplitude"]))
+    dt = np.longdouble if ld else np.float64
+    a = np.array(u, dtype=np.float64).astype(dt).ravel().copy()
+    b = np.array(ut, dtype=np.float64).astype(dt).ravel().copy()
+    sx = np.ascontiguousarray(np.asarray(source["x"], dtype=np.float64).astype(dt))
+    rc = load(ld).oracle_run_forced(n, m, float(cfl), float(c), q, int(nsteps), _ptr(a), _ptr(b), _ptr(sx),
+                                    float(source["sigma"]), float(source["freq"]), float(source["t0"]),
+                                    float(source["amplitude"]))
     if rc != 0:
         raise ValueError(f"oracle_run_forced failed: {rc}")
-    return a.reshape(shape), b.reshape(shape)
+    return a.astype(np.float64).reshape(shape), b.astype(np.float64).reshape(shape)

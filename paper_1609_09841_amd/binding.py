@@ -38,7 +38,7 @@ EVOLUTIONS = {"taylor": HERMITE_EVOLVE_TAYLOR, "rk4": HERMITE_EVOLVE_RK4}
 EXPORTS = (
     "hermite_default_options", "hermite_create", "hermite_set_initial", "hermite_set_initial_device",
     "hermite_step", "hermite_gather", "hermite_gather_device", "hermite_sync", "hermite_get_time",
-    "hermite_destroy", "hermite_last_error",
+    "hermite_destroy", "hermite_last_error", "hermite_set_source",
 )
 
 
@@ -52,6 +52,16 @@ class hermite_options(ctypes.Structure):
         ("poison", ctypes.c_int),
         ("kernel", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+class hermite_source(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_double * 3),
+        ("sigma", ctypes.c_double),
+        ("freq", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("amplitude", ctypes.c_double),
     ]
 
 
@@ -95,6 +105,8 @@ def load(path: str = LIB_PATH):
     lib.hermite_get_time.restype = ip
     lib.hermite_destroy.argtypes = [vp]
     lib.hermite_destroy.restype = None
+    lib.hermite_set_source.argtypes = [vp, ctypes.POINTER(hermite_source)]
+    lib.hermite_set_source.restype = ip
     lib.hermite_last_error.argtypes = [vp]
     lib.hermite_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -125,6 +137,18 @@ def hermite_create(n_cells: int, m: int, cfl: float, c: float, opt: hermite_opti
     rc = load().hermite_create(int(n_cells), int(m), float(cfl), float(c),
                                ctypes.byref(opt) if opt is not None else None, ctypes.byref(h))
     return rc, (h if rc == HERMITE_OK else None)
+
+
+def hermite_set_source(ctx, src: hermite_source | None) -> int:
+    return load().hermite_set_source(ctx, ctypes.byref(src) if src is not None else None)
+
+
+def make_source(x, sigma: float, freq: float, t0: float, amplitude: float) -> hermite_source:
+    s = hermite_source()
+    for i in range(3):
+        s.x[i] = float(x[i])
+    s.sigma, s.freq, s.t0, s.amplitude = float(sigma), float(freq), float(t0), float(amplitude)
+    return s
 
 
 def hermite_last_error(ctx=None) -> str:
@@ -175,6 +199,12 @@ class Solver:
         b = np.ascontiguousarray(np.asarray(ut, dtype=np.float64)).ravel()
         assert a.size == self.size and b.size == self.size
         _check(self._lib.hermite_set_initial(self._ctx, _dptr(a), _dptr(b)), self._ctx)
+
+    def set_source(self, source: dict | None):
+        """Point source {"x", "sigma", "freq", "t0", "amplitude"}; None removes it."""
+        src = None if source is None else make_source(source["x"], source["sigma"], source["freq"],
+                                                     source["t0"], source["amplitude"])
+        _check(hermite_set_source(self._ctx, src), self._ctx)
 
     def step(self, nsteps: int = 1):
         _check(self._lib.hermite_step(self._ctx, int(nsteps)), self._ctx)

@@ -39,6 +39,8 @@ struct hermite_ctx {
     size_t grid_doubles = 0;
     bool has_state = false;
     long long steps = 0;
+    bool has_source = false;
+    hermite_source source{};               // x reduced to [0, 1)
     std::string err;
 };
 
@@ -89,6 +91,78 @@ int select_device(hermite_ctx* ctx) {
     return HERMITE_OK;
 }
 
+// Time Taylor coefficients w_k = tau^k/k! w^(k)(ta), k < K, of the Ricker
+// wavelet w = (1 - 2 beta s^2) exp(-beta s^2). With z = sqrt(2 beta) s,
+// w = -He_2(z) exp(-z^2/2), and since d/dz [He_n(z) exp(-z^2/2)] =
+// -He_{n+1}(z) exp(-z^2/2), w^(k) = -(-sqrt(2 beta))^k He_{k+2}(z) exp(-z^2/2)
+// (He: probabilists' Hermite polynomials).
+void ricker_coefficients(long double ta, long double tau, long double f0, long double t0, int K,
+                         long double* w) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    const long double r = sqrtl(2.0L) * pi * f0;  // sqrt(2 beta)
+    const long double z = r * (ta - t0);
+    const long double g = expl(-0.5L * z * z);
+    long double hprev = 1.0L, h = z;  // He_0, He_1
+    long double scale = 1.0L;         // (-r tau)^k / k!
+    for (int n = 1; n < K + 1; ++n) {  // advance to He_{n+1}
+        const long double nxt = z * h - (long double)n * hprev;
+        hprev = h;
+        h = nxt;
+        const int k = n - 1;  // now h = He_{k+2}
+        if (k > 0) scale *= -r * tau / (long double)k;
+        w[k] = -scale * h * g;
+    }
+}
+
+// Scalars of the particular solution of one half step starting at ta (the
+// kernel's P_u = sum_i A_i Lap^i G, P_vt = sum_i B_i Lap^i G), each already
+// multiplied by i!. See the derivation at the top of the source kernel.
+hermite::SourceScalars source_scalars(const hermite_ctx* ctx, long double ta) {
+    const int q = ctx->q;
+    long double w[64];
+    ricker_coefficients(ta, ctx->tau, ctx->source.freq, ctx->source.t0, q, w);
+    const long double lam = ctx->lam, pre = (long double)ctx->tau * ctx->h / ctx->c;
+    hermite::SourceScalars sc{};
+    long double ifact = 1.0L;
+    for (int i = 0; i <= 3 * ctx->m && i < 10; ++i) {
+        if (i > 0) ifact *= i;
+        long double a = 0.0L, b = 0.0L;
+        for (int k = 0; k + 1 + 2 * i <= q; ++k) {
+            long double rb = 1.0L;  // k! / (k + 1 + 2i)!
+            for (int l = k + 1; l <= k + 1 + 2 * i; ++l) rb /= l;
+            b += w[k] * rb;
+            if (k + 2 + 2 * i <= q) a += w[k] * rb / (long double)(k + 2 + 2 * i);
+        }
+        const long double l2i = powl(lam, 2 * i);
+        sc.Ai[i] = (double)(pre * a * l2i * lam * ifact);
+        sc.Bi[i] = (double)(pre * b * l2i * ifact);
+    }
+    return sc;
+}
+
+// Cells (per axis, a periodic run of indices) whose centres may lie within
+// 6 sigma of the source; the kernel applies the exact cut-off per cell.
+hermite::SourceBox source_box(const hermite_ctx* ctx, int to_dual) {
+    const int n = ctx->n;
+    const double off = to_dual ? 0.5 : 1.0;  // centre of cell i at (i + off) h
+    const double R = 6.0 * ctx->source.sigma * n;
+    uint32_t lo[3], cnt[3];
+    for (int x = 0; x < 3; ++x) {
+        const double S = ctx->source.x[x] * n;
+        const double a = std::floor(S - R - off) - 1.0, b = std::ceil(S + R - off) + 1.0;
+        if (b - a + 1.0 >= (double)n) {
+            lo[x] = 0;
+            cnt[x] = (uint32_t)n;
+        } else {
+            long long i0 = (long long)a % n;
+            if (i0 < 0) i0 += n;
+            lo[x] = (uint32_t)i0;
+            cnt[x] = (uint32_t)(b - a + 1.0);
+        }
+    }
+    return hermite::SourceBox{lo[0], lo[1], lo[2], cnt[0], cnt[1], cnt[2]};
+}
+
 int half_step(hermite_ctx* ctx, int from) {
     const double* src = ctx->grid[from];
     double* dst = ctx->grid[1 - from];
@@ -116,6 +190,14 @@ int half_step(hermite_ctx* ctx, int from) {
         e = hermite::launch_evolve(ctx->m, ctx->R, dst, ctx->n, ctx->pitch, off, ctx->opt.evolution, ctx->q,
                                    ctx->substeps, ctx->lam, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "evolution launch");
+    }
+    if (ctx->has_source) {
+        const long double ta = (long double)ctx->steps * ctx->dt + (from ? (long double)ctx->tau : 0.0L);
+        const int to_dual = (from == 0);
+        const hermite::SourceScalars sc = source_scalars(ctx, ta);
+        e = hermite::launch_source(dst, ctx->n, ctx->pitch, ctx->m, source_box(ctx, to_dual), ctx->source.x, ctx->h,
+                                   ctx->source.sigma, ctx->source.amplitude, to_dual, sc, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "source launch");
     }
     return HERMITE_OK;
 }
@@ -329,6 +411,28 @@ int hermite_gather_device(hermite_ctx* ctx, void* u_dev, void* ut_dev) {
         HCHECK(ctx, hermite::launch_scale((double*)ut_dev, ctx->ncell, gv, ctx->pitch, ctx->c / ctx->h, ctx->ncell,
                                           ctx->M3, ctx->stream),
                "scale ut");
+    return HERMITE_OK;
+}
+
+int hermite_set_source(hermite_ctx* ctx, const hermite_source* src) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!src || src->amplitude == 0.0) {
+        ctx->has_source = false;
+        return HERMITE_OK;
+    }
+    for (int x = 0; x < 3; ++x)
+        if (!std::isfinite(src->x[x])) return fail(ctx, HERMITE_EINVAL, "source x[%d] not finite", x);
+    if (!std::isfinite(src->sigma) || !(src->sigma > 0.0))
+        return fail(ctx, HERMITE_EINVAL, "source sigma=%g must be finite and > 0", src->sigma);
+    if (!std::isfinite(src->freq) || src->freq < 0.0)
+        return fail(ctx, HERMITE_EINVAL, "source freq=%g must be finite and >= 0", src->freq);
+    if (!std::isfinite(src->t0) || !std::isfinite(src->amplitude))
+        return fail(ctx, HERMITE_EINVAL, "source t0 and amplitude must be finite");
+    if (ctx->opt.evolution != HERMITE_EVOLVE_TAYLOR)
+        return fail(ctx, HERMITE_EUNSUPPORTED, "the point source needs Taylor evolution");
+    ctx->source = *src;
+    for (double& v : ctx->source.x) v -= std::floor(v);
+    ctx->has_source = true;
     return HERMITE_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 
 namespace hermite {
 
@@ -51,6 +52,22 @@ hipError_t launch_fused_mixed(int precision, const double* src, double* dst, con
                               int off, int grid, hipStream_t st);
 size_t mixed_operator_bytes(int precision);
 void mixed_build_operators(int precision, const double* K, void* out);
+
+// Point source: per-half-step scalars (A_i i!, B_i i!, i <= 3m) and the box
+// of source-grid cells (lower corners x0.., periodic, nx x ny x nz) whose
+// centres lie within 6 sigma of the source along every axis.
+struct SourceScalars {
+    double Ai[10];
+    double Bi[10];
+};
+struct SourceBox {
+    uint32_t x0, y0, z0, nx, ny, nz;
+};
+// Adds the particular solution of the forced cell system to the new nodes of
+// the box's cells (stream-ordered after the half step that wrote dst).
+hipError_t launch_source(double* dst, int n, size_t pitch, int m, const SourceBox& box, const double* centre,
+                         double h, double sigma, double amp, int to_dual, const SourceScalars& sc,
+                         hipStream_t st);
 
 // Interpolation half of the two-kernel variant: writes the monomial
 // coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity

@@ -83,6 +83,7 @@ def test_null_context_calls_fail_cleanly():
     assert lib.hermite_set_initial(None, None, None) == B.HERMITE_EINVAL
     assert lib.hermite_gather(None, None, None, None) == B.HERMITE_EINVAL
     assert lib.hermite_get_time(None, None, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_set_source(None, None) == B.HERMITE_EINVAL
     lib.hermite_destroy(None)  # no-op
     assert isinstance(lib.hermite_last_error(None), bytes)
 
