@@ -627,3 +627,87 @@ int oracle_run_forced(int n, int m, real cfl, real c, int q, int nsteps, real *u
     free(b);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Advection (Sec. 2, Eq. 1), the equation the paper measures: one field with
+ * the scaled derivatives of order <= m per axis at every node, on the same
+ * primal/dual grids. Here with a speed c: u_t = c (u_x1 + u_x2 + u_x3), c = 1
+ * being the paper's equation. In the cell variable xi and the half-step time
+ * sigma = (t - t_n)/tau the equation reads u_sigma = lam (sum_x d/dxi_x) u
+ * with lam = c tau / h, so the Cauchy-Kovalevskaya recursion of Eq. 5 (its
+ * Delta t read as the half step, as for the wave system) is
+ *   b_{j, s+1} = lam / (s + 1) sum_x (j_x + 1) b_{j + e_x, s},
+ * and the q-stage Horner loop of Alg. 4 sums the series at sigma = 1. The
+ * stage count q = 3(2m+1) of Sec. 3.2 is exact for this equation.
+ * ------------------------------------------------------------------------ */
+
+/* Sum over the three axes of Alg. 3: (G W)[j] = sum_x (j_x + 1) W[j + e_x]. */
+static void or_grad_sum(int P, const real *W, real *out)
+{
+    const int n3 = P * P * P;
+    real d[OR_MAXP * OR_MAXP * OR_MAXP];
+    for (int t = 0; t < n3; ++t) out[t] = 0.0;
+    for (int axis = 0; axis < 3; ++axis) {
+        or_diff_axis(P, axis, W, d);
+        for (int t = 0; t < n3; ++t) out[t] += d[t];
+    }
+}
+
+/* Alg. 4 for advection: W <- R + (lam / k) G W for k = q .. 1. */
+void oracle_evolve_advection(int m, int q, real lam, real *R)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    real w[OR_MAXP * OR_MAXP * OR_MAXP], g[OR_MAXP * OR_MAXP * OR_MAXP];
+    memcpy(w, R, sizeof(real) * n3);
+    for (int k = q; k >= 1; --k) {
+        or_grad_sum(P, w, g);
+        for (int t = 0; t < n3; ++t) w[t] = R[t] + (lam / (real)k) * g[t];
+    }
+    memcpy(R, w, sizeof(real) * n3);
+}
+
+/* One advection half step over the whole grid (one field of (m+1)^3 columns). */
+void oracle_half_step_advection(int n, int m, const real *H, real lam, int q, const real *src, real *dst,
+                                int to_dual)
+{
+    const int M = m + 1, P = 2 * M;
+    const int off = to_dual ? 0 : 1;
+    const long nn = (long)n * n * n;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j) {
+            real uloc[OR_MAXP * OR_MAXP * OR_MAXP], R[OR_MAXP * OR_MAXP * OR_MAXP];
+            for (int i = 0; i < n; ++i) {
+                oracle_gather_cell(n, m, src, i, j, k, uloc);
+                oracle_interpolate_cell(m, H, uloc, R);
+                oracle_evolve_advection(m, q, lam, R);
+                const long node = ((long)((k + off) % n) * n + (j + off) % n) * n + (i + off) % n;
+                for (int d3 = 0; d3 < M; ++d3)
+                    for (int d2 = 0; d2 < M; ++d2)
+                        for (int d1 = 0; d1 < M; ++d1)
+                            dst[(long)((d3 * M + d2) * M + d1) * nn + node] = R[(d3 * P + d2) * P + d1];
+            }
+        }
+}
+
+/* nsteps full advection steps of the primal-grid field u ((m+1)^3 n^3
+ * values, layout of oracle_run), dt = cfl h / c. */
+int oracle_run_advection(int n, int m, real cfl, real c, int q, int nsteps, real *u)
+{
+    if (n < 1 || m < 1 || m > OR_MAXM || !(cfl > 0.0) || !(c > 0.0) || nsteps < 0 || q < 1 || q > 64)
+        return -1;
+    const int M = m + 1, M3 = M * M * M;
+    const long sz = (long)M3 * n * n * n;
+    const real h = 1.0 / (real)n;
+    const real dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    real H[OR_MAXP * OR_MAXP];
+    if (oracle_hermite_matrix(m, H) != 0) return -2;
+    real *b = (real *)malloc(sizeof(real) * sz);
+    if (!b) return -3;
+    for (int s = 0; s < nsteps; ++s) {
+        oracle_half_step_advection(n, m, H, lam, q, u, b, 1);
+        oracle_half_step_advection(n, m, H, lam, q, b, u, 0);
+    }
+    free(b);
+    return 0;
+}

@@ -28,6 +28,7 @@ __all__ = [
     "interpolate_cell", "laplacian", "evolve_taylor", "evolve_rk4",
     "gather_cell", "half_step", "run", "point", "point_box", "exact_q",
     "gauss_taylor", "ricker_taylor", "evolve_taylor_forced", "run_forced",
+    "advection_q", "evolve_advection", "run_advection",
 ]
 
 
@@ -84,6 +85,12 @@ def load(ld: bool = False):
     lib.oracle_evolve_taylor_forced.restype = None
     lib.oracle_run_forced.argtypes = [i, i, d, d, i, i, dp, dp, dp, d, d, d, d]
     lib.oracle_run_forced.restype = i
+    lib.oracle_evolve_advection.argtypes = [i, i, d, dp]
+    lib.oracle_evolve_advection.restype = None
+    lib.oracle_half_step_advection.argtypes = [i, i, dp, d, i, dp, dp, i]
+    lib.oracle_half_step_advection.restype = None
+    lib.oracle_run_advection.argtypes = [i, i, d, d, i, i, dp]
+    lib.oracle_run_advection.restype = i
     if ld:
         _lib_ld = lib
     else:
@@ -322,3 +329,34 @@ def run_forced(n: int, m: int, cfl: float, c: float, u, ut, nsteps: int, source:
     if rc != 0:
         raise ValueError(f"oracle_run_forced failed: {rc}")
     return a.astype(np.float64).reshape(shape), b.astype(np.float64).reshape(shape)
+
+
+# --- advection (the paper's Eq. 1) -------------------------------------------
+
+def advection_q(m: int) -> int:
+    """Stage count 3(2m+1) of Sec. 3.2: exact for the advection equation."""
+    return 3 * (2 * m + 1)
+
+
+def evolve_advection(m: int, q: int, lam: float, R: np.ndarray) -> np.ndarray:
+    """Alg. 4 for u_sigma = lam (sum_x d/dxi_x) u on one cell's coefficients R[j3][j2][j1]."""
+    P = 2 * m + 2
+    a = np.array(R, dtype=np.float64).reshape(P, P, P).copy()
+    load().oracle_evolve_advection(m, int(q), float(lam), _ptr(a))
+    return a
+
+
+def run_advection(n: int, m: int, cfl: float, c: float, u, nsteps: int, q: int | None = None,
+                  ld: bool = False) -> np.ndarray:
+    """nsteps full steps of u_t = c (u_x1 + u_x2 + u_x3) from primal-grid data u
+    ((m+1)^3 n^3 scaled derivatives, layout [d3][d2][d1][k][j][i]).
+    ld=True runs the long-double twin (rounding-floor measurements only)."""
+    q = advection_q(m) if q is None else int(q)
+    shape = np.shape(u)
+    dt = np.longdouble if ld else np.float64
+    a = np.array(u, dtype=np.float64).astype(dt).ravel().copy()
+    assert a.size == (m + 1) ** 3 * n ** 3
+    rc = load(ld).oracle_run_advection(n, m, float(cfl), float(c), q, int(nsteps), _ptr(a))
+    if rc != 0:
+        raise ValueError(f"oracle_run_advection failed: {rc}")
+    return a.astype(np.float64).reshape(shape)
