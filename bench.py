@@ -18,6 +18,10 @@ Also reported (outside the timed region of the headline):
   * precision study: 256^3 cells, m = 3, 200 steps, final-time rel L2 of the
     mixed paths against the plain FP64 GPU path (whose parity with the CPU
     oracle is tested separately);
+  * batched point-source workload: 64 seeded shots of uneven sizes and
+    orders, one Gaussian/Ricker source each, 150 steps, stepped together by
+    the batch API (graph replay, autotuned launch shapes), FP32 and FP64,
+    against the same shots run one after the other;
   * the CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
@@ -94,6 +98,8 @@ def parse():
     ap.add_argument("--all-variants", action="store_true", help="also time the other three variants")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-precision-study", action="store_true", help="skip the 256^3 precision study")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched point-source leg")
+    ap.add_argument("--batch-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96, help="grid of the oracle's timed sample")
     return ap.parse_args()
@@ -156,6 +162,86 @@ def precision_study(B, torch, I, n=256, m=3, steps=200) -> dict:
         del u, ut
     del u0, ut0, ru, rut
     torch.cuda.empty_cache()
+    return out
+
+
+def batch_leg(B, torch, I, steps: int = 150, warmup: int = 2, count: int = 64) -> dict:
+    """The batched point-source workload: `count` seeded shots of uneven sizes
+    and orders (inputs.batch_shots), zero data, one source each, stepped
+    together (one graph replay per full step, autotuned launch shapes). FP32
+    contractions for the m = 3 shots (m = 1, 2 shots run FP64); error stated
+    against the same batch in FP64; compared with the shots run one after the
+    other as single-grid contexts."""
+    shots = I.batch_shots(count=count)
+    dof = sum(2 * (sh["m"] + 1) ** 3 * sh["n"] ** 3 * 2 for sh in shots)      # DOF-updates per full step
+    hbm = sum(2 * 32 * (sh["m"] + 1) ** 3 * sh["n"] ** 3 for sh in shots)     # algorithmic bytes per full step
+    m3 = [i for i, sh in enumerate(shots) if sh["m"] == 3]
+    out = {"workload": f"{count} shots, n from {{32,48,64,96}} and m from {{1,2,3}} by seed, zero data, "
+                       f"Gaussian source (sigma 2h) with a Ricker wavelet (f0 = c/(8h), t0 = 1.2/f0), "
+                       f"{steps} steps, cfl 0.5",
+           "dof_updates_per_step": dof, "steps": steps}
+    finals = {}
+    for prec in ("fp64", "fp32"):
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream), B.Batch(shots, precision=prec, stream=stream) as b:
+            b.step(warmup)            # graph capture and first replays
+            for i in range(len(shots)):
+                b.set_initial(i)      # every shot back to zero data at t = 0
+            b.sync()
+            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            b.step(steps)
+            end.record(stream)
+            end.synchronize()
+            ms = start.elapsed_time(end)
+            tuning = {}
+            for m in (1, 2, 3):
+                try:
+                    ch, tms = b.tuning(m)
+                    tuning[f"m{m}"] = {"choice": ch, "half_step_ms": tms}
+                except B.HermiteError:
+                    pass
+            res = {"value": dof * steps / (ms / 1e3), "unit": "DOF-updates/s", "ms_per_step": ms / steps,
+                   "hbm_GBps_algorithmic": hbm * steps / (ms / 1e3) / 1e9, "autotune": tuning}
+            if prec == "fp64":
+                for i in m3:
+                    finals[i] = b.gather(i)[:2]
+            else:
+                worst = {"u": 0.0, "u_t": 0.0, "u_nodes": 0.0, "u_t_nodes": 0.0}
+                for i in m3:
+                    u, ut, _ = b.gather(i)
+                    ru, rut = finals[i]
+                    e = errors(I, u, ut, ru, rut)
+                    worst = {k: max(worst[k], e[k]) for k in worst}
+                res["rel_l2_vs_fp64_worst_m3_shot"] = worst
+        out[prec] = res
+    finals.clear()
+    # the same shots one after the other, each its own single-grid context
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    solvers = []
+    with torch.cuda.stream(stream):
+        for sh in shots:
+            s = B.Solver(sh["n"], sh["m"], 0.5, 1.0, stream=stream, precision="fp32" if sh["m"] == 3 else "fp64")
+            M, n = sh["m"] + 1, sh["n"]
+            z = torch.zeros((M, M, M, n, n, n), dtype=torch.float64, device="cuda")
+            s.set_initial(z, z)
+            s.set_source(sh["source"])
+            solvers.append(s)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for s in solvers:
+            s.step(steps)
+        end.record(stream)
+        end.synchronize()
+        sms = start.elapsed_time(end)
+    for s in solvers:
+        s.close()
+    torch.cuda.empty_cache()
+    out["sequential_single_contexts_fp32"] = {"value": dof * steps / (sms / 1e3), "ms_per_step": sms / steps}
+    out["batch_speedup_vs_sequential"] = sms / (out["fp32"]["ms_per_step"] * steps)
     return out
 
 
@@ -262,6 +348,8 @@ def main():
         del u0, ut0
         torch.cuda.empty_cache()
         out["precision_study"] = precision_study(B, torch, I)
+    if not args.no_batch:
+        out["batch"] = batch_leg(B, torch, I, steps=args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_n)
     print(json.dumps(out), flush=True)

@@ -180,6 +180,80 @@ void hermite_destroy(hermite_ctx *ctx);
  * (for failures of hermite_create). Never NULL; "" when there was none. */
 const char *hermite_last_error(const hermite_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent shots. A batch owns many grids of uneven sizes and
+ * orders that share cfl and c (each with its own h = 1/n and dt = cfl h / c)
+ * and step together: every half step runs one launch per order present,
+ * each covering all shots of that order, then one launch for all point
+ * sources (the same half step as hermite_step, Sec. 2-3, per shot).
+ * ------------------------------------------------------------------------ */
+typedef struct hermite_batch hermite_batch; /* opaque; owns all device memory */
+
+typedef struct hermite_shot {
+    int n_cells;           /* cells per side, 2 .. 1290 */
+    int m;                 /* derivatives per dimension, 1 .. 3 */
+    int has_source;        /* 1: `source` forces this shot (as hermite_set_source) */
+    hermite_source source;
+} hermite_shot;
+
+typedef struct hermite_batch_options {
+    int precision;   /* HERMITE_PREC_* of the m = 3 shots; m = 1, 2 shots
+                        always run the FP64 kernels */
+    int evolution;   /* HERMITE_EVOLVE_*; sources need Taylor */
+    int rk_substeps; /* as hermite_options */
+    int q;           /* as hermite_options */
+    int graph;       /* 1 (default): hermite_batch_step replays one captured
+                        HIP graph per full step (order groups on parallel
+                        branches); 0: direct launches on the stream */
+    int autotune;    /* 1 (default): hermite_batch_create times every
+                        candidate launch shape of each order group on the
+                        batch's own grids and keeps the fastest; 0: defaults */
+    void *stream;    /* hipStream_t; NULL -> a stream owned by the batch */
+} hermite_batch_options;
+
+/* Defaults: FP64, Taylor q = 6m+1, graph on, autotune on, own stream. */
+void hermite_batch_default_options(hermite_batch_options *opt);
+
+/*
+ * Creates a batch of n_shots (1 .. 4096) shots, all at t = 0 with zero data.
+ * shots: n_shots descriptions (copied; validated as hermite_create and
+ * hermite_set_source validate theirs: HERMITE_EINVAL, HERMITE_EUNSUPPORTED
+ * for a source with RK4 evolution). Allocates two grids per shot (layout of
+ * hermite_create), zero-fills them and, with autotune, runs each candidate
+ * shape on the dual grids (which hold no state between full steps).
+ */
+int hermite_batch_create(int n_shots, const hermite_shot *shots, double cfl, double c,
+                         const hermite_batch_options *opt, hermite_batch **out);
+
+/* Sets shot `shot` (0-based) from host arrays (layout and scaling of
+ * hermite_set_initial; NULL u and ut: zero data) and restarts its clock at
+ * t = 0. Waits for the batch's stream first; copies synchronously. */
+int hermite_batch_set_initial(hermite_batch *b, int shot, const double *u, const double *ut);
+
+/* Enqueues n_full_steps full steps of every shot (async, n_full_steps >= 0). */
+int hermite_batch_step(hermite_batch *b, int n_full_steps);
+
+/* Waits, then copies shot `shot`'s state to host arrays (either may be NULL)
+ * and its time t = steps * dt into *t_out (may be NULL). */
+int hermite_batch_gather(hermite_batch *b, int shot, double *u, double *ut, double *t_out);
+
+/* Waits for all work enqueued on the batch's stream. */
+int hermite_batch_sync(hermite_batch *b);
+
+/* Launch shape chosen for the shots of order m (HERMITE_EINVAL if the batch
+ * has none): *choice indexes the candidates (m = 1, 2: blocks of 64, 128,
+ * 256 cells; m = 3: item runs of 1 or 4 batches, XCD-sliced or
+ * interleaved, in that order) and *ms its measured half-step time (0 when
+ * not tuned). Either pointer may be NULL. */
+int hermite_batch_tuning(const hermite_batch *b, int m, int *choice, double *ms);
+
+/* Waits for outstanding work and frees everything. NULL is a no-op. */
+void hermite_batch_destroy(hermite_batch *b);
+
+/* Last error of b, or of the calling thread's last failed
+ * hermite_batch_create when b is NULL. Never NULL. */
+const char *hermite_batch_last_error(const hermite_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,9 @@ EXPORTS = (
     "hermite_default_options", "hermite_create", "hermite_set_initial", "hermite_set_initial_device",
     "hermite_step", "hermite_gather", "hermite_gather_device", "hermite_sync", "hermite_get_time",
     "hermite_destroy", "hermite_last_error", "hermite_set_source",
+    "hermite_batch_default_options", "hermite_batch_create", "hermite_batch_set_initial", "hermite_batch_step",
+    "hermite_batch_gather", "hermite_batch_sync", "hermite_batch_tuning", "hermite_batch_destroy",
+    "hermite_batch_last_error",
 )
 
 
@@ -62,6 +65,27 @@ class hermite_source(ctypes.Structure):
         ("freq", ctypes.c_double),
         ("t0", ctypes.c_double),
         ("amplitude", ctypes.c_double),
+    ]
+
+
+class hermite_shot(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int),
+        ("m", ctypes.c_int),
+        ("has_source", ctypes.c_int),
+        ("source", hermite_source),
+    ]
+
+
+class hermite_batch_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("evolution", ctypes.c_int),
+        ("rk_substeps", ctypes.c_int),
+        ("q", ctypes.c_int),
+        ("graph", ctypes.c_int),
+        ("autotune", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -109,6 +133,26 @@ def load(path: str = LIB_PATH):
     lib.hermite_set_source.restype = ip
     lib.hermite_last_error.argtypes = [vp]
     lib.hermite_last_error.restype = ctypes.c_char_p
+    bopt_p = ctypes.POINTER(hermite_batch_options)
+    lib.hermite_batch_default_options.argtypes = [bopt_p]
+    lib.hermite_batch_default_options.restype = None
+    lib.hermite_batch_create.argtypes = [ip, ctypes.POINTER(hermite_shot), ctypes.c_double, ctypes.c_double, bopt_p,
+                                         ctypes.POINTER(vp)]
+    lib.hermite_batch_create.restype = ip
+    lib.hermite_batch_set_initial.argtypes = [vp, ip, dp, dp]
+    lib.hermite_batch_set_initial.restype = ip
+    lib.hermite_batch_step.argtypes = [vp, ip]
+    lib.hermite_batch_step.restype = ip
+    lib.hermite_batch_gather.argtypes = [vp, ip, dp, dp, dp]
+    lib.hermite_batch_gather.restype = ip
+    lib.hermite_batch_sync.argtypes = [vp]
+    lib.hermite_batch_sync.restype = ip
+    lib.hermite_batch_tuning.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int), dp]
+    lib.hermite_batch_tuning.restype = ip
+    lib.hermite_batch_destroy.argtypes = [vp]
+    lib.hermite_batch_destroy.restype = None
+    lib.hermite_batch_last_error.argtypes = [vp]
+    lib.hermite_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -235,6 +279,121 @@ class Solver:
         if getattr(self, "_ctx", None) is not None:
             self._lib.hermite_destroy(self._ctx)
             self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --- batches of independent shots -------------------------------------------
+
+def hermite_batch_default_options() -> hermite_batch_options:
+    o = hermite_batch_options()
+    load().hermite_batch_default_options(ctypes.byref(o))
+    return o
+
+
+def make_shots(shots) -> ctypes.Array:
+    """shots: list of {"n": cells per side, "m": order, "source": dict or None}."""
+    arr = (hermite_shot * len(shots))()
+    for i, sh in enumerate(shots):
+        arr[i].n_cells = int(sh["n"])
+        arr[i].m = int(sh["m"])
+        src = sh.get("source")
+        arr[i].has_source = int(src is not None)
+        if src is not None:
+            arr[i].source = make_source(src["x"], src["sigma"], src["freq"], src["t0"], src["amplitude"])
+    return arr
+
+
+def hermite_batch_create(shots, cfl: float, c: float, opt: hermite_batch_options | None = None):
+    """Returns (status, batch handle or None)."""
+    arr = make_shots(shots)
+    h = ctypes.c_void_p()
+    rc = load().hermite_batch_create(len(shots), arr, float(cfl), float(c),
+                                     ctypes.byref(opt) if opt is not None else None, ctypes.byref(h))
+    return rc, (h if rc == HERMITE_OK else None)
+
+
+def hermite_batch_last_error(b=None) -> str:
+    return load().hermite_batch_last_error(b).decode(errors="replace")
+
+
+def _bcheck(rc: int, b=None):
+    if rc != HERMITE_OK:
+        raise HermiteError(rc, hermite_batch_last_error(b))
+
+
+class Batch:
+    """One hermite_batch: independent shots of uneven sizes and orders stepped
+    together. Host arrays are numpy float64 of shape (M, M, M, n, n, n)."""
+
+    def __init__(self, shots, cfl: float = 0.5, c: float = 1.0, *, precision: str = "fp64",
+                 evolution: str = "taylor", q: int = 0, rk_substeps: int = 1, graph: bool = True,
+                 autotune: bool = True, stream=None):
+        lib = load()
+        o = hermite_batch_default_options()
+        o.precision = PRECISIONS[precision]
+        o.evolution = EVOLUTIONS[evolution]
+        o.q = int(q)
+        o.rk_substeps = int(rk_substeps)
+        o.graph = int(bool(graph))
+        o.autotune = int(bool(autotune))
+        if stream is not None:
+            o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self.shots = [dict(sh) for sh in shots]
+        self._stream = stream
+        rc, h = hermite_batch_create(self.shots, cfl, c, o)
+        _bcheck(rc, None)
+        self._b = h
+        self._lib = lib
+
+    def __len__(self):
+        return len(self.shots)
+
+    def set_initial(self, shot: int, u=None, ut=None):
+        if u is None and ut is None:
+            _bcheck(self._lib.hermite_batch_set_initial(self._b, int(shot), None, None), self._b)
+            return
+        sh = self.shots[shot]
+        size = (sh["m"] + 1) ** 3 * sh["n"] ** 3
+        a = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        b = np.ascontiguousarray(np.asarray(ut, dtype=np.float64)).ravel()
+        assert a.size == size and b.size == size
+        _bcheck(self._lib.hermite_batch_set_initial(self._b, int(shot), _dptr(a), _dptr(b)), self._b)
+
+    def step(self, nsteps: int = 1):
+        _bcheck(self._lib.hermite_batch_step(self._b, int(nsteps)), self._b)
+
+    def sync(self):
+        _bcheck(self._lib.hermite_batch_sync(self._b), self._b)
+
+    def gather(self, shot: int):
+        sh = self.shots[shot]
+        M, n = sh["m"] + 1, sh["n"]
+        u = np.empty((M, M, M, n, n, n))
+        ut = np.empty_like(u)
+        t = ctypes.c_double()
+        _bcheck(self._lib.hermite_batch_gather(self._b, int(shot), _dptr(u), _dptr(ut), ctypes.byref(t)), self._b)
+        return u, ut, t.value
+
+    def tuning(self, m: int):
+        ch, ms = ctypes.c_int(), ctypes.c_double()
+        _bcheck(self._lib.hermite_batch_tuning(self._b, int(m), ctypes.byref(ch), ctypes.byref(ms)), self._b)
+        return ch.value, ms.value
+
+    def close(self):
+        if getattr(self, "_b", None) is not None:
+            self._lib.hermite_batch_destroy(self._b)
+            self._b = None
 
     def __enter__(self):
         return self

@@ -17,6 +17,7 @@
 
 #include "hermite.h"
 #include "constants.h"
+#include "host_common.h"
 #include "kernels.h"
 
 struct hermite_ctx {
@@ -40,7 +41,9 @@ struct hermite_ctx {
     bool has_state = false;
     long long steps = 0;
     bool has_source = false;
-    hermite_source source{};               // x reduced to [0, 1)
+    hermite::SourceDesc* d_source = nullptr;  // one device entry
+    uint32_t* d_source_prefix = nullptr;      // [from][2] block offsets
+    uint32_t source_blocks[2] = {0, 0};
     std::string err;
 };
 
@@ -76,91 +79,14 @@ void free_all(hermite_ctx* ctx) {
     if (ctx->R) { (void)hipFree(ctx->R); ctx->R = nullptr; }
     if (ctx->K) { (void)hipFree(ctx->K); ctx->K = nullptr; }
     if (ctx->Hp) { (void)hipFree(ctx->Hp); ctx->Hp = nullptr; }
+    if (ctx->d_source) { (void)hipFree(ctx->d_source); ctx->d_source = nullptr; }
+    if (ctx->d_source_prefix) { (void)hipFree(ctx->d_source_prefix); ctx->d_source_prefix = nullptr; }
     if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
 }
-
-// Column pitch of the device grids: n^3 rounded up to whole 256-byte blocks,
-// plus 5 cache lines (640 bytes). With the unpadded power-of-two strides of
-// the common grid sizes, the 2 M^3 columns of one node (and of its
-// neighbours) all map to the same L2 set and channel, and the cache holds
-// almost none of the data that the 8 cells around a node share.
-size_t column_pitch(size_t ncell) { return ((ncell + 31) / 32) * 32 + 80; }
 
 int select_device(hermite_ctx* ctx) {
     HCHECK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     return HERMITE_OK;
-}
-
-// Time Taylor coefficients w_k = tau^k/k! w^(k)(ta), k < K, of the Ricker
-// wavelet w = (1 - 2 beta s^2) exp(-beta s^2). With z = sqrt(2 beta) s,
-// w = -He_2(z) exp(-z^2/2), and since d/dz [He_n(z) exp(-z^2/2)] =
-// -He_{n+1}(z) exp(-z^2/2), w^(k) = -(-sqrt(2 beta))^k He_{k+2}(z) exp(-z^2/2)
-// (He: probabilists' Hermite polynomials).
-void ricker_coefficients(long double ta, long double tau, long double f0, long double t0, int K,
-                         long double* w) {
-    const long double pi = 3.14159265358979323846264338327950288L;
-    const long double r = sqrtl(2.0L) * pi * f0;  // sqrt(2 beta)
-    const long double z = r * (ta - t0);
-    const long double g = expl(-0.5L * z * z);
-    long double hprev = 1.0L, h = z;  // He_0, He_1
-    long double scale = 1.0L;         // (-r tau)^k / k!
-    for (int n = 1; n < K + 1; ++n) {  // advance to He_{n+1}
-        const long double nxt = z * h - (long double)n * hprev;
-        hprev = h;
-        h = nxt;
-        const int k = n - 1;  // now h = He_{k+2}
-        if (k > 0) scale *= -r * tau / (long double)k;
-        w[k] = -scale * h * g;
-    }
-}
-
-// Scalars of the particular solution of one half step starting at ta (the
-// kernel's P_u = sum_i A_i Lap^i G, P_vt = sum_i B_i Lap^i G), each already
-// multiplied by i!. See the derivation at the top of the source kernel.
-hermite::SourceScalars source_scalars(const hermite_ctx* ctx, long double ta) {
-    const int q = ctx->q;
-    long double w[64];
-    ricker_coefficients(ta, ctx->tau, ctx->source.freq, ctx->source.t0, q, w);
-    const long double lam = ctx->lam, pre = (long double)ctx->tau * ctx->h / ctx->c;
-    hermite::SourceScalars sc{};
-    long double ifact = 1.0L;
-    for (int i = 0; i <= 3 * ctx->m && i < 10; ++i) {
-        if (i > 0) ifact *= i;
-        long double a = 0.0L, b = 0.0L;
-        for (int k = 0; k + 1 + 2 * i <= q; ++k) {
-            long double rb = 1.0L;  // k! / (k + 1 + 2i)!
-            for (int l = k + 1; l <= k + 1 + 2 * i; ++l) rb /= l;
-            b += w[k] * rb;
-            if (k + 2 + 2 * i <= q) a += w[k] * rb / (long double)(k + 2 + 2 * i);
-        }
-        const long double l2i = powl(lam, 2 * i);
-        sc.Ai[i] = (double)(pre * a * l2i * lam * ifact);
-        sc.Bi[i] = (double)(pre * b * l2i * ifact);
-    }
-    return sc;
-}
-
-// Cells (per axis, a periodic run of indices) whose centres may lie within
-// 6 sigma of the source; the kernel applies the exact cut-off per cell.
-hermite::SourceBox source_box(const hermite_ctx* ctx, int to_dual) {
-    const int n = ctx->n;
-    const double off = to_dual ? 0.5 : 1.0;  // centre of cell i at (i + off) h
-    const double R = 6.0 * ctx->source.sigma * n;
-    uint32_t lo[3], cnt[3];
-    for (int x = 0; x < 3; ++x) {
-        const double S = ctx->source.x[x] * n;
-        const double a = std::floor(S - R - off) - 1.0, b = std::ceil(S + R - off) + 1.0;
-        if (b - a + 1.0 >= (double)n) {
-            lo[x] = 0;
-            cnt[x] = (uint32_t)n;
-        } else {
-            long long i0 = (long long)a % n;
-            if (i0 < 0) i0 += n;
-            lo[x] = (uint32_t)i0;
-            cnt[x] = (uint32_t)(b - a + 1.0);
-        }
-    }
-    return hermite::SourceBox{lo[0], lo[1], lo[2], cnt[0], cnt[1], cnt[2]};
 }
 
 int half_step(hermite_ctx* ctx, int from) {
@@ -192,11 +118,8 @@ int half_step(hermite_ctx* ctx, int from) {
         if (e != hipSuccess) return hip_fail(ctx, e, "evolution launch");
     }
     if (ctx->has_source) {
-        const long double ta = (long double)ctx->steps * ctx->dt + (from ? (long double)ctx->tau : 0.0L);
-        const int to_dual = (from == 0);
-        const hermite::SourceScalars sc = source_scalars(ctx, ta);
-        e = hermite::launch_source(dst, ctx->n, ctx->pitch, ctx->m, source_box(ctx, to_dual), ctx->source.x, ctx->h,
-                                   ctx->source.sigma, ctx->source.amplitude, to_dual, sc, ctx->stream);
+        e = hermite::launch_source(ctx->d_source, ctx->d_source_prefix + 2 * from, 1, ctx->source_blocks[from], from,
+                                   ctx->steps, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "source launch");
     }
     return HERMITE_OK;
@@ -244,7 +167,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
 
     const int M = m + 1, P = 2 * m + 2;
     const size_t nn = (size_t)n_cells * n_cells * n_cells;
-    const size_t pitch = column_pitch(nn);
+    const size_t pitch = hermite::column_pitch(nn);
     const size_t grid_doubles = (size_t)2 * M * M * M * pitch;
     const size_t r_doubles = o.fused ? 0 : (size_t)2 * P * P * P * pitch;
 
@@ -420,18 +343,27 @@ int hermite_set_source(hermite_ctx* ctx, const hermite_source* src) {
         ctx->has_source = false;
         return HERMITE_OK;
     }
-    for (int x = 0; x < 3; ++x)
-        if (!std::isfinite(src->x[x])) return fail(ctx, HERMITE_EINVAL, "source x[%d] not finite", x);
-    if (!std::isfinite(src->sigma) || !(src->sigma > 0.0))
-        return fail(ctx, HERMITE_EINVAL, "source sigma=%g must be finite and > 0", src->sigma);
-    if (!std::isfinite(src->freq) || src->freq < 0.0)
-        return fail(ctx, HERMITE_EINVAL, "source freq=%g must be finite and >= 0", src->freq);
-    if (!std::isfinite(src->t0) || !std::isfinite(src->amplitude))
-        return fail(ctx, HERMITE_EINVAL, "source t0 and amplitude must be finite");
+    const std::string why = hermite::check_source(*src);
+    if (!why.empty()) return fail(ctx, HERMITE_EINVAL, "%s", why.c_str());
     if (ctx->opt.evolution != HERMITE_EVOLVE_TAYLOR)
         return fail(ctx, HERMITE_EUNSUPPORTED, "the point source needs Taylor evolution");
-    ctx->source = *src;
-    for (double& v : ctx->source.x) v -= std::floor(v);
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    hermite::SourceDesc d = hermite::make_source_desc(*src, ctx->n, ctx->m, ctx->q, ctx->cfl, ctx->c);
+    d.grid[0] = ctx->grid[0];
+    d.grid[1] = ctx->grid[1];
+    d.pitch = ctx->pitch;
+    d.steps = 0;  // unused: the host passes the step count at each launch
+    const uint32_t blocks[2] = {hermite::source_blocks(d, 0), hermite::source_blocks(d, 1)};
+    const uint32_t prefix[4] = {0, blocks[0], 0, blocks[1]};
+    if (!ctx->d_source) HCHECK(ctx, hipMalloc(&ctx->d_source, sizeof(d)), "hipMalloc(source)");
+    if (!ctx->d_source_prefix) HCHECK(ctx, hipMalloc(&ctx->d_source_prefix, sizeof(prefix)), "hipMalloc(source)");
+    // earlier half steps may still read the old entry
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_source");
+    HCHECK(ctx, hipMemcpy(ctx->d_source, &d, sizeof(d), hipMemcpyHostToDevice), "upload source");
+    HCHECK(ctx, hipMemcpy(ctx->d_source_prefix, prefix, sizeof(prefix), hipMemcpyHostToDevice), "upload source");
+    ctx->source_blocks[0] = blocks[0];
+    ctx->source_blocks[1] = blocks[1];
     ctx->has_source = true;
     return HERMITE_OK;
 }

@@ -26,6 +26,7 @@
 #include <cstdint>
 #include <cstring>
 
+#include "batch_common.h"
 #include "fused_common.h"
 #include "kernels.h"
 
@@ -145,41 +146,79 @@ __device__ __forceinline__ void store_batch(double* __restrict__ dst, size_t pla
     }
 }
 
+// One batch: 16 neighbouring cells of one x-row (cells x0 .. x0+15 of row
+// (y, z); lanes past the end of the row compute a copy of the last cell and
+// store nothing).
+template <int PREC>
+__device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t pitch,
+                                          uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
+                                          int cl, int q, const unsigned char* sbuf) {
+    const uint32_t x = x0 + cl;
+    const bool valid = x < n;
+    const Cell16 c = cell_nodes((z * n + y) * n + (valid ? x : n - 1), n, off);
+    const double* base = src + (size_t)(32 * q) * pitch;
+    // opaque per batch, so per-step addresses are not hoisted out of the sweep
+    asm volatile("" : "+v"(base));
+    f4 acc[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
+    double P0[8][4];
+    double ring[kRing][8];
+    Prologue<kAhead<PREC>, 0>::run(base, pitch, c, ring);
+    if constexpr (PREC == 1) {
+        StepsF32<0>::run(base, pitch, c, lane, (const float*)sbuf, acc, P0, ring);
+    } else {
+        s4 Bhi[8], Blo[8];
+        StepsBf16<0>::run(base, pitch, c, lane, (const s4*)sbuf, acc, P0, ring, Bhi, Blo);
+    }
+    if (valid) store_batch(dst, pitch, c, q, acc, P0);
+}
+
+template <int PREC>
+__device__ __forceinline__ void load_operator(const void* __restrict__ Aops, unsigned char* sbuf) {
+    constexpr int kBytes = (PREC == 1) ? kF32Floats * 4 : kBf16Vecs * 8;
+    const uint4* g = (const uint4*)Aops;
+    uint4* l = (uint4*)sbuf;
+    for (int i = threadIdx.x; i < kBytes / 16; i += blockDim.x) l[i] = g[i];
+    __syncthreads();
+}
+
+template <int PREC>
+constexpr int kOpBytes = (PREC == 1) ? kF32Floats * 4 : kBf16Vecs * 8;
+
 template <int PREC>  // 1 = FP32, 2 = BF16x3
 __global__ __launch_bounds__(kWaves * 64) void fused_mixed_kernel(const double* __restrict__ src,
                                                                   double* __restrict__ dst,
                                                                   const void* __restrict__ Aops, uint32_t n,
                                                                   size_t pitch, uint32_t off) {
-    constexpr int kBytes = (PREC == 1) ? kF32Floats * 4 : kBf16Vecs * 8;
-    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kBytes];
-    {
-        const uint4* g = (const uint4*)Aops;
-        uint4* l = (uint4*)sbuf;
-        for (int i = threadIdx.x; i < kBytes / 16; i += blockDim.x) l[i] = g[i];
-    }
-    __syncthreads();
+    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<PREC>];
+    load_operator<PREC>(Aops, sbuf);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
     fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
-        const uint32_t x = x0 + cl;
-        const bool valid = x < n;
-        const Cell16 c = cell_nodes((z * n + y) * n + (valid ? x : n - 1), n, off);
-        const double* base = src + (size_t)(32 * q) * pitch;
-        // opaque per batch, so per-step addresses are not hoisted out of the sweep
-        asm volatile("" : "+v"(base));
-        f4 acc[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
-        double P0[8][4];
-        double ring[kRing][8];
-        Prologue<kAhead<PREC>, 0>::run(base, pitch, c, ring);
-        if constexpr (PREC == 1) {
-            StepsF32<0>::run(base, pitch, c, lane, (const float*)sbuf, acc, P0, ring);
-        } else {
-            s4 Bhi[8], Blo[8];
-            StepsBf16<0>::run(base, pitch, c, lane, (const s4*)sbuf, acc, P0, ring, Bhi, Blo);
-        }
-        if (valid) store_batch(dst, pitch, c, q, acc, P0);
+        run_batch<PREC>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, sbuf);
+    });
+}
+
+// Batched: the 16-cell batches of every shot of the group (batch_common.h).
+template <int PREC>
+__global__ __launch_bounds__(kWaves * 64) void fused_mixed_batch_kernel(const batch::ShotGrid* __restrict__ shots,
+                                                                        const uint32_t* __restrict__ ids,
+                                                                        const uint32_t* __restrict__ prefix,
+                                                                        uint32_t ng, uint32_t from,
+                                                                        const void* __restrict__ Aops,
+                                                                        uint32_t chunk, uint32_t interleaved) {
+    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<PREC>];
+    load_operator<PREC>(Aops, sbuf);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    batch::sweep_items(prefix[ng], wave, kWaves, chunk, interleaved, [&](uint32_t it) {
+        const uint32_t g = batch::find_entry(prefix, ng, it);
+        const batch::ShotGrid& S = shots[ids[g]];
+        const uint32_t n = S.n, nbx = (n + 15) >> 4, local = it - prefix[g];
+        const uint32_t bx = local % nbx, row = local / nbx;
+        run_batch<PREC>(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, row % n, row / n, lane, cl, q,
+                        sbuf);
     });
 }
 
@@ -233,6 +272,21 @@ void mixed_build_operators(int precision, const double* K, void* out) {
                         A[((((size_t)p * 8 + ks) * 2 + 1) * 64 + lane) * 4 + e] = lo;
                     }
     }
+}
+
+hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots, const uint32_t* ids,
+                                    const uint32_t* prefix, uint32_t ng, int from, const void* Aops, int grid,
+                                    uint32_t chunk, uint32_t interleaved, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0 || chunk < 1) return hipErrorInvalidValue;
+    if (precision == 1)
+        hipLaunchKernelGGL(fused_mixed_batch_kernel<1>, dim3(grid), dim3(kWaves * 64), 0, st, shots, ids, prefix, ng,
+                           (uint32_t)from, Aops, chunk, interleaved);
+    else if (precision == 2)
+        hipLaunchKernelGGL(fused_mixed_batch_kernel<2>, dim3(grid), dim3(kWaves * 64), 0, st, shots, ids, prefix, ng,
+                           (uint32_t)from, Aops, chunk, interleaved);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_fused_mixed(int precision, const double* src, double* dst, const void* Aops, int n, size_t pitch,

@@ -17,6 +17,7 @@
 
 #include <cstdint>
 
+#include "batch_common.h"
 #include "fused_common.h"
 #include "kernels.h"
 
@@ -162,15 +163,11 @@ struct SmallCols {
 };
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void fused_valu_small_kernel(const double* __restrict__ src,
-                                                                    double* __restrict__ dst,
-                                                                    const double* __restrict__ Kv, uint32_t n,
-                                                                    size_t pitch, uint32_t off) {
+__device__ __forceinline__ void small_cell(const double* __restrict__ src, double* __restrict__ dst,
+                                           const double* __restrict__ Kv, uint32_t n, size_t pitch, uint32_t off,
+                                           uint32_t cell) {
     constexpr SmallLayout<M> L{};
     constexpr int NO = SmallLayout<M>::NO;
-    const uint32_t ncell = n * n * n;
-    const uint32_t cell = blockIdx.x * kThreads + threadIdx.x;
-    if (cell >= ncell) return;
     const Cell16 c = cell_nodes(cell, n, off);
     double acc[NO];
 #pragma unroll
@@ -178,6 +175,47 @@ __global__ __launch_bounds__(kThreads) void fused_valu_small_kernel(const double
     SmallCols<M, 0>::run(src, pitch, c, Kv, acc);
 #pragma unroll
     for (int o = 0; o < NO; ++o) dst[(size_t)L.out_j[o] * pitch + c.out] = acc[o];
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void fused_valu_small_kernel(const double* __restrict__ src,
+                                                                    double* __restrict__ dst,
+                                                                    const double* __restrict__ Kv, uint32_t n,
+                                                                    size_t pitch, uint32_t off) {
+    const uint32_t cell = blockIdx.x * kThreads + threadIdx.x;
+    if (cell >= n * n * n) return;
+    small_cell<M>(src, dst, Kv, n, pitch, off, cell);
+}
+
+// Batched: work item = a block of BS cells of one shot (batch_common.h).
+template <int M, int BS>
+__global__ __launch_bounds__(BS) void fused_valu_small_batch_kernel(const batch::ShotGrid* __restrict__ shots,
+                                                                    const uint32_t* __restrict__ ids,
+                                                                    const uint32_t* __restrict__ prefix, uint32_t ng,
+                                                                    uint32_t from, const double* __restrict__ Kv) {
+    const uint32_t g = batch::find_entry(prefix, ng, blockIdx.x);
+    const batch::ShotGrid& S = shots[ids[g]];
+    const uint32_t n = S.n;
+    const uint32_t cell = (blockIdx.x - prefix[g]) * BS + threadIdx.x;
+    if (cell >= n * n * n) return;
+    small_cell<M>(S.grid[from], S.grid[1 - from], Kv, n, S.pitch, from, cell);
+}
+
+template <int M>
+hipError_t launch_small_batch(int bs, const batch::ShotGrid* shots, const uint32_t* ids, const uint32_t* prefix,
+                              uint32_t ng, uint32_t blocks, int from, const double* Kv, hipStream_t st) {
+    if (bs == 64)
+        hipLaunchKernelGGL((fused_valu_small_batch_kernel<M, 64>), dim3(blocks), dim3(64), 0, st, shots, ids, prefix,
+                           ng, (uint32_t)from, Kv);
+    else if (bs == 128)
+        hipLaunchKernelGGL((fused_valu_small_batch_kernel<M, 128>), dim3(blocks), dim3(128), 0, st, shots, ids,
+                           prefix, ng, (uint32_t)from, Kv);
+    else if (bs == 256)
+        hipLaunchKernelGGL((fused_valu_small_batch_kernel<M, 256>), dim3(blocks), dim3(256), 0, st, shots, ids,
+                           prefix, ng, (uint32_t)from, Kv);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <int M>
@@ -212,6 +250,15 @@ hipError_t launch_fused_valu_small(int m, const double* src, double* dst, const 
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_fused_valu_small_batch(int m, int block, const batch::ShotGrid* shots, const uint32_t* ids,
+                                         const uint32_t* prefix, uint32_t ng, uint32_t blocks, int from,
+                                         const double* Kv, hipStream_t st) {
+    if (blocks == 0) return hipSuccess;
+    if (m == 1) return launch_small_batch<2>(block, shots, ids, prefix, ng, blocks, from, Kv, st);
+    if (m == 2) return launch_small_batch<3>(block, shots, ids, prefix, ng, blocks, from, Kv, st);
+    return hipErrorInvalidValue;
 }
 
 size_t valu4_operator_doubles() { return (size_t)2 * 128 * 64; }

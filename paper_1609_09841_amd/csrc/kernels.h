@@ -53,21 +53,50 @@ hipError_t launch_fused_mixed(int precision, const double* src, double* dst, con
 size_t mixed_operator_bytes(int precision);
 void mixed_build_operators(int precision, const double* K, void* out);
 
-// Point source: per-half-step scalars (A_i i!, B_i i!, i <= 3m) and the box
-// of source-grid cells (lower corners x0.., periodic, nx x ny x nz) whose
-// centres lie within 6 sigma of the source along every axis.
-struct SourceScalars {
-    double Ai[10];
-    double Bi[10];
+// Point source (one entry per forced grid, device-resident). The source
+// kernel adds the particular solution of the forced cell system to the new
+// nodes of the cells of box[from] (stream-ordered after the half step that
+// wrote grid[1 - from]).
+struct SourceDesc {
+    double* grid[2];     // primal, dual
+    uint64_t pitch;      // doubles between columns
+    uint32_t n, m, q;    // cells per side, order, Taylor stages
+    uint32_t box[2][6];  // per half step (from = 0, 1): first cell x, y, z
+                         // (periodic) and counts nx, ny, nz of the source-grid
+                         // cells whose centres may lie within 6 sigma
+    double x[3];         // source point in [0, 1)^3
+    double sigma, amp, f0, t0;
+    double h, tau, dt, lam, pre;  // pre = tau h / c
+    int64_t steps;       // full steps taken: the device-side clock
 };
-struct SourceBox {
-    uint32_t x0, y0, z0, nx, ny, nz;
-};
-// Adds the particular solution of the forced cell system to the new nodes of
-// the box's cells (stream-ordered after the half step that wrote dst).
-hipError_t launch_source(double* dst, int n, size_t pitch, int m, const SourceBox& box, const double* centre,
-                         double h, double sigma, double amp, int to_dual, const SourceScalars& sc,
-                         hipStream_t st);
+// Blocks the source kernel needs for entry s in half step `from`.
+uint32_t source_blocks(const SourceDesc& s, int from);
+// srcs: ns device entries; prefix: ns + 1 device block offsets for this half
+// step (prefix[ns] = blocks). host_steps >= 0 replaces every entry's clock.
+hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_t ns, uint32_t blocks, int from,
+                         long long host_steps, hipStream_t st);
+// steps += 1 for every entry (end of a full step of a batch).
+hipError_t launch_advance_clock(SourceDesc* srcs, uint32_t ns, hipStream_t st);
+
+// Batched fused half steps (batch_common.h): one launch over the shots of one
+// order. ids/prefix: group entries and their first work item (ng + 1
+// entries, device); from: 0 primal -> dual, 1 dual -> primal. Operators as
+// for the single-grid launches (they depend on m and lam only).
+//   m = 1, 2: work item = `block` cells (64, 128 or 256); blocks = prefix[ng].
+//   m = 3 FP64 and mixed: 16-cell batches; persistent grid (multiple of 8);
+//   chunk/interleaved select the item order (batch::sweep_items).
+namespace batch {
+struct ShotGrid;
+}
+hipError_t launch_fused_valu_small_batch(int m, int block, const batch::ShotGrid* shots, const uint32_t* ids,
+                                         const uint32_t* prefix, uint32_t ng, uint32_t blocks, int from,
+                                         const double* Kv, hipStream_t st);
+hipError_t launch_fused_mfma_batch(const batch::ShotGrid* shots, const uint32_t* ids, const uint32_t* prefix,
+                                   uint32_t ng, int from, const double* Kperm, int grid, uint32_t chunk,
+                                   uint32_t interleaved, hipStream_t st);
+hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots, const uint32_t* ids,
+                                    const uint32_t* prefix, uint32_t ng, int from, const void* Aops, int grid,
+                                    uint32_t chunk, uint32_t interleaved, hipStream_t st);
 
 // Interpolation half of the two-kernel variant: writes the monomial
 // coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity

@@ -19,7 +19,7 @@ import torch
 
 __all__ = [
     "fourier_modes", "fourier_initial", "fourier_exact", "standing_mode",
-    "plane_waves_1d", "rel_l2",
+    "plane_waves_1d", "rel_l2", "batch_shots",
 ]
 
 
@@ -123,3 +123,23 @@ def rel_l2(x, ref) -> float:
     den = torch.linalg.vector_norm(ref).item()
     num = torch.linalg.vector_norm(x - ref).item()
     return num / den if den > 0 else num
+
+
+def batch_shots(seed: int = 1609, count: int = 64, sizes=(32, 48, 64, 96), orders=(1, 2, 3), c: float = 1.0):
+    """Seeded shot list of the batched point-source workload: per shot, in
+    this draw order, cells per side from `sizes`, order m from `orders`, and
+    the source point uniform in [0, 1)^3. Each source is a Gaussian of width
+    sigma = 2h with a Ricker wavelet of about 8 cells per dominant wavelength
+    (f0 = c / (8h)) peaking at t0 = 1.2 / f0, unit amplitude; zero initial
+    data. Shot dicts: {"n", "m", "source": {"x", "sigma", "freq", "t0",
+    "amplitude"}}."""
+    rng = np.random.default_rng(seed)
+    shots = []
+    for _ in range(count):
+        n = int(rng.choice(sizes))
+        m = int(rng.choice(orders))
+        x = tuple(float(v) for v in rng.uniform(0.0, 1.0, 3))
+        f0 = c * n / 8.0
+        shots.append({"n": n, "m": m, "source": {"x": x, "sigma": 2.0 / n, "freq": f0, "t0": 1.2 / f0,
+                                                  "amplitude": 1.0}})
+    return shots

@@ -113,3 +113,68 @@ def test_mixed_precision_needs_m3_fused(precision, m, fused):
     rc, h = B.hermite_create(8, m, 0.5, 1.0, o)
     assert rc == B.HERMITE_EUNSUPPORTED and h is None
     assert "precision" in B.hermite_last_error(None)
+
+
+# --- batches ------------------------------------------------------------------
+
+def _src():
+    return {"x": (0.3, 0.4, 0.5), "sigma": 0.05, "freq": 4.0, "t0": 0.3, "amplitude": 1.0}
+
+
+def test_batch_default_options():
+    o = B.hermite_batch_default_options()
+    assert (o.precision, o.evolution, o.rk_substeps, o.q, o.graph, o.autotune) == (0, 0, 1, 0, 1, 1)
+    assert o.stream is None
+
+
+@pytest.mark.parametrize("shots,kw,what", [
+    ([], {}, "n_shots"),
+    ([{"n": 1, "m": 1}], {}, "n_cells"),
+    ([{"n": 8, "m": 4}], {}, "m="),
+    ([{"n": 8, "m": 2}, {"n": 1291, "m": 1}], {}, "shot 1"),
+    ([{"n": 8, "m": 2}], {"cfl": 0.0}, "cfl"),
+    ([{"n": 8, "m": 2}], {"cfl": float("nan")}, "cfl"),
+    ([{"n": 8, "m": 2}], {"c": -1.0}, "c="),
+    ([{"n": 8, "m": 2, "source": dict(_src(), sigma=0.0)}], {}, "sigma"),
+    ([{"n": 8, "m": 2, "source": dict(_src(), freq=-2.0)}], {}, "freq"),
+    ([{"n": 8, "m": 2, "source": dict(_src(), x=(0.1, float("inf"), 0.0))}], {}, "x[1]"),
+])
+def test_batch_create_validates_before_any_device_call(shots, kw, what):
+    rc, h = B.hermite_batch_create(shots, kw.get("cfl", 0.5), kw.get("c", 1.0))
+    assert rc == B.HERMITE_EINVAL and h is None
+    assert what in B.hermite_batch_last_error(None)
+
+
+@pytest.mark.parametrize("field,value", [("precision", 3), ("evolution", 2), ("q", 65), ("rk_substeps", -1),
+                                         ("graph", 2), ("autotune", -1)])
+def test_batch_options_validated(field, value):
+    o = B.hermite_batch_default_options()
+    setattr(o, field, value)
+    rc, h = B.hermite_batch_create([{"n": 8, "m": 1}], 0.5, 1.0, o)
+    assert rc == B.HERMITE_EINVAL and h is None
+    assert field.split("_")[0] in B.hermite_batch_last_error(None)
+
+
+def test_batch_source_needs_taylor():
+    o = B.hermite_batch_default_options()
+    o.evolution = B.HERMITE_EVOLVE_RK4
+    rc, h = B.hermite_batch_create([{"n": 8, "m": 1, "source": _src()}], 0.5, 1.0, o)
+    assert rc == B.HERMITE_EUNSUPPORTED and h is None
+
+
+def test_batch_null_handles():
+    lib = B.load()
+    assert lib.hermite_batch_step(None, 1) == B.HERMITE_EINVAL
+    assert lib.hermite_batch_sync(None) == B.HERMITE_EINVAL
+    assert lib.hermite_batch_set_initial(None, 0, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_batch_gather(None, 0, None, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_batch_tuning(None, 1, None, None) == B.HERMITE_EINVAL
+    lib.hermite_batch_destroy(None)
+    assert isinstance(lib.hermite_batch_last_error(None), bytes)
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_valid_batch_create_without_device_reports_device_error():
+    rc, h = B.hermite_batch_create([{"n": 8, "m": 1}, {"n": 6, "m": 3}], 0.5, 1.0)
+    assert rc == B.HERMITE_EDEVICE and h is None
+    assert B.hermite_batch_last_error(None) != ""
