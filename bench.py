@@ -22,6 +22,8 @@ Also reported (outside the timed region of the headline):
     orders, one Gaussian/Ricker source each, 150 steps, stepped together by
     the batch API (graph replay, autotuned launch shapes), FP32 and FP64,
     against the same shots run one after the other;
+  * the paper's advection workload (Eq. 1): 150^3 cells, 200 steps, m = 1..3,
+    time to solution next to the paper's (GTX 980, FP32: context only);
   * the CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
@@ -99,6 +101,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-precision-study", action="store_true", help="skip the 256^3 precision study")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched point-source leg")
+    ap.add_argument("--no-advection", action="store_true", help="skip the advection leg")
     ap.add_argument("--batch-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96, help="grid of the oracle's timed sample")
@@ -245,6 +248,45 @@ def batch_leg(B, torch, I, steps: int = 150, warmup: int = 2, count: int = 64) -
     return out
 
 
+# Time to solution of the paper's advection table (150^3 grid points, 200
+# steps, GTX 980, FP32, monolithic kernel), seconds per order m: context only.
+PAPER_ADVECTION_S = {1: 2.09, 2: 13.77, 3: 36.17}
+
+
+def advection_leg(B, torch, I, n: int = 150, steps: int = 200, warmup: int = 1) -> dict:
+    """The paper's advection workload (Eq. 1): n^3 cells, 200 steps, m = 1..3,
+    seeded Fourier-mode data, fused FP64 kernel (the exact series composed with
+    interpolation into one separable operator per axis)."""
+    out = {"workload": f"advection u_t = u_x1 + u_x2 + u_x3, {n}^3 periodic cells, {steps} steps, cfl 0.5, "
+                       f"seeded Fourier modes, fused FP64",
+           "paper_context": "GTX 980, FP32, monolithic kernel: " +
+                            ", ".join(f"m={m} {t} s" for m, t in PAPER_ADVECTION_S.items())}
+    for m in (1, 2, 3):
+        u0, _ = I.fourier_initial(n, m, device="cuda")
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream), B.Solver(n, m, 0.5, 1.0, equation="advection", stream=stream) as s:
+            s.set_initial(u0)
+            s.step(warmup)
+            s.set_initial(u0)
+            s.sync()
+            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            s.step(steps)
+            end.record(stream)
+            end.synchronize()
+            ms = start.elapsed_time(end)
+        dof = (m + 1) ** 3 * n ** 3 * 2 * steps            # one field, two half steps per step
+        gbs = 16 * dof / (ms / 1e3) / 1e9                  # 8 B read + 8 B written per DOF-update
+        out[f"m{m}"] = {"time_to_solution_s": ms / 1e3, "value": dof / (ms / 1e3), "unit": "DOF-updates/s",
+                        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": gbs / HBM_PEAK_GBS, "kernel": f"advect_kernel<{m + 1}>"},
+                        "paper_time_s": PAPER_ADVECTION_S[m]}
+        del u0
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(m: int, n_s: int) -> dict:
     """The oracle (plain FP64 C, OpenMP) on a bounded sample of the workload:
     the same data recipe and order on an n_s^3 grid, one full step."""
@@ -348,6 +390,8 @@ def main():
         del u0, ut0
         torch.cuda.empty_cache()
         out["precision_study"] = precision_study(B, torch, I)
+    if not args.no_advection:
+        out["advection"] = advection_leg(B, torch, I)
     if not args.no_batch:
         out["batch"] = batch_leg(B, torch, I, steps=args.batch_steps)
     if not args.no_cpu_baseline:

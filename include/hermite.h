@@ -62,6 +62,15 @@ extern "C" {
 #define HERMITE_KERNEL_MFMA 1  /* FP64 matrix cores (v_mfma_f64_16x16x4) */
 #define HERMITE_KERNEL_VALU 2  /* FP64 vector FMAs, operator entries as scalar operands */
 
+/* Equation (Sec. 2). WAVE: u_tt = c^2 Lap u as the first-order system
+ * (u, u_t), two fields per node. ADVECTION: u_t = c (u_x1 + u_x2 + u_x3),
+ * the paper's Eq. 1 (c = 1), one field per node: set_initial and gather then
+ * ignore ut (it may be NULL). Advection needs FP64, Taylor evolution with
+ * q = 0 or q >= 3(2m+1) (the series is then exact, Sec. 3.2) and the fused
+ * kernel, HERMITE_EUNSUPPORTED otherwise; it has no point source. */
+#define HERMITE_EQ_WAVE 0
+#define HERMITE_EQ_ADVECTION 1
+
 #define HERMITE_EVOLVE_TAYLOR 0 /* Sec. 3.2, Alg. 4: q-stage Taylor series (Horner) */
 #define HERMITE_EVOLVE_RK4 1    /* classical 4-stage Runge-Kutta on the cell ODE */
 
@@ -71,9 +80,10 @@ typedef struct hermite_options {
     int precision;   /* HERMITE_PREC_*; default FP64 */
     int evolution;   /* HERMITE_EVOLVE_*; default Taylor */
     int rk_substeps; /* RK4 substeps per half step, >= 1; 0 -> 1 */
-    int q;           /* Taylor stages, 1..64; 0 -> 6m+1, the exact count for
-                        this system (the paper's d(2N+1) = 6m+3 gives the same
-                        result up to rounding, Sec. 3.2) */
+    int q;           /* Taylor stages, 1..64; 0 -> the exact count: 6m+1 for
+                        the wave system (the paper's d(2N+1) = 6m+3 gives the
+                        same result up to rounding, Sec. 3.2), 3(2m+1) for
+                        advection */
     int fused;       /* 1: one kernel per half step (Sec. 3.3, monolithic);
                         0: interpolation and evolution kernels with the
                         reconstructed coefficients in device memory
@@ -81,6 +91,7 @@ typedef struct hermite_options {
     int poison;      /* debug: 1 fills each destination grid with NaN before
                         the half step that writes it */
     int kernel;      /* fused FP64 kernel for m = 3: HERMITE_KERNEL_* */
+    int equation;    /* HERMITE_EQ_*; default WAVE */
     void *stream;    /* hipStream_t to run on; NULL -> a stream owned by the
                         context. Caller keeps a given stream alive until
                         hermite_destroy. */
@@ -97,13 +108,15 @@ void hermite_default_options(hermite_options *opt);
  *            (Sec. 2: waves must not cross from the cell boundary to its centre
  *            in a half step) is necessary; in 3D the Taylor method is stable
  *            up to about 0.8 and RK4 (1 substep) up to 0.5.
- *   c:       wave speed, > 0 and finite
+ *   c:       wave speed (advection: the speed along each axis), > 0 and
+ *            finite
  *   opt:     NULL for defaults
  *   out:     receives the context; untouched on failure
  * Arguments are validated before any HIP call: invalid arguments return
  * HERMITE_EINVAL (HERMITE_EUNSUPPORTED for a valid but unsupported option
  * combination) even without a device. Allocates two FP64 grids of
- * 2*(m+1)^3 columns of n^3 doubles each, plus 2*(2m+2)^3 columns when
+ * 2*(m+1)^3 columns of n^3 doubles each ((m+1)^3 for advection), plus
+ * 2*(2m+2)^3 columns when
  * fused == 0; each device column is padded by at most 112 doubles.
  * No kernel runs.
  */

@@ -29,6 +29,9 @@ HERMITE_EVOLVE_RK4 = 1
 HERMITE_KERNEL_AUTO = 0
 HERMITE_KERNEL_MFMA = 1
 HERMITE_KERNEL_VALU = 2
+HERMITE_EQ_WAVE = 0
+HERMITE_EQ_ADVECTION = 1
+EQUATIONS = {"wave": HERMITE_EQ_WAVE, "advection": HERMITE_EQ_ADVECTION}
 KERNELS = {"auto": HERMITE_KERNEL_AUTO, "mfma": HERMITE_KERNEL_MFMA, "valu": HERMITE_KERNEL_VALU}
 
 PRECISIONS = {"fp64": HERMITE_PREC_FP64, "fp32": HERMITE_PREC_FP32, "bf16x3": HERMITE_PREC_BF16X3}
@@ -54,6 +57,7 @@ class hermite_options(ctypes.Structure):
         ("fused", ctypes.c_int),
         ("poison", ctypes.c_int),
         ("kernel", ctypes.c_int),
+        ("equation", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -207,7 +211,7 @@ class Solver:
 
     def __init__(self, n: int, m: int, cfl: float = 0.5, c: float = 1.0, *, precision: str = "fp64",
                  evolution: str = "taylor", q: int = 0, rk_substeps: int = 1, fused: bool = True,
-                 poison: bool = False, kernel: str = "auto", stream=None):
+                 poison: bool = False, kernel: str = "auto", equation: str = "wave", stream=None):
         lib = load()
         o = hermite_default_options()
         o.precision = PRECISIONS[precision]
@@ -217,6 +221,8 @@ class Solver:
         o.fused = int(bool(fused))
         o.poison = int(bool(poison))
         o.kernel = KERNELS[kernel]
+        o.equation = EQUATIONS[equation]
+        self.nf = 1 if equation == "advection" else 2
         if stream is not None:
             o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
         self.n, self.m = int(n), int(m)
@@ -232,16 +238,22 @@ class Solver:
     def handle(self):
         return self._ctx
 
-    def set_initial(self, u, ut):
+    def set_initial(self, u, ut=None):
+        """ut is ignored (may be None) for advection."""
         if hasattr(u, "is_cuda") and u.is_cuda:
-            assert u.dtype == ut.dtype and str(u.dtype) == "torch.float64"
-            assert u.is_contiguous() and ut.is_contiguous() and u.numel() == self.size == ut.numel()
-            _check(self._lib.hermite_set_initial_device(self._ctx, ctypes.c_void_p(u.data_ptr()),
-                                                        ctypes.c_void_p(ut.data_ptr())), self._ctx)
+            assert str(u.dtype) == "torch.float64" and u.is_contiguous() and u.numel() == self.size
+            vp = ctypes.c_void_p(ut.data_ptr()) if (ut is not None and self.nf == 2) else None
+            if self.nf == 2:
+                assert ut.dtype == u.dtype and ut.is_contiguous() and ut.numel() == self.size
+            _check(self._lib.hermite_set_initial_device(self._ctx, ctypes.c_void_p(u.data_ptr()), vp), self._ctx)
             return
         a = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        assert a.size == self.size
+        if self.nf == 1:
+            _check(self._lib.hermite_set_initial(self._ctx, _dptr(a), None), self._ctx)
+            return
         b = np.ascontiguousarray(np.asarray(ut, dtype=np.float64)).ravel()
-        assert a.size == self.size and b.size == self.size
+        assert b.size == self.size
         _check(self._lib.hermite_set_initial(self._ctx, _dptr(a), _dptr(b)), self._ctx)
 
     def set_source(self, source: dict | None):
@@ -257,18 +269,23 @@ class Solver:
         _check(self._lib.hermite_sync(self._ctx), self._ctx)
 
     def gather(self):
-        """(u, ut, t) as numpy arrays shaped (M, M, M, n, n, n)."""
+        """(u, ut, t) as numpy arrays shaped (M, M, M, n, n, n); ut is None
+        for advection."""
         M, n = self.m + 1, self.n
         u = np.empty((M, M, M, n, n, n))
-        ut = np.empty_like(u)
+        ut = np.empty_like(u) if self.nf == 2 else None
         t = ctypes.c_double()
-        _check(self._lib.hermite_gather(self._ctx, _dptr(u), _dptr(ut), ctypes.byref(t)), self._ctx)
+        _check(self._lib.hermite_gather(self._ctx, _dptr(u), _dptr(ut) if ut is not None else None,
+                                        ctypes.byref(t)), self._ctx)
         return u, ut, t.value
 
-    def gather_device(self, u, ut):
-        assert u.is_cuda and ut.is_cuda and u.numel() == self.size == ut.numel()
-        _check(self._lib.hermite_gather_device(self._ctx, ctypes.c_void_p(u.data_ptr()),
-                                               ctypes.c_void_p(ut.data_ptr())), self._ctx)
+    def gather_device(self, u, ut=None):
+        assert u.is_cuda and u.numel() == self.size
+        vp = None
+        if ut is not None and self.nf == 2:
+            assert ut.is_cuda and ut.numel() == self.size
+            vp = ctypes.c_void_p(ut.data_ptr())
+        _check(self._lib.hermite_gather_device(self._ctx, ctypes.c_void_p(u.data_ptr()), vp), self._ctx)
 
     def time(self):
         t, s, dt = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()

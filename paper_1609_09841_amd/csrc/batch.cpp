@@ -68,10 +68,13 @@ struct hermite_batch {
     Group groups[3];                              // m = 1, 2, 3
     // sources
     std::vector<int> src_entry;                   // entry of each shot, -1 without
-    std::vector<hermite::SourceDesc> srcs;
+    std::vector<hermite::SourceDesc> srcs;        // sorted by order m
     hermite::SourceDesc* d_srcs = nullptr;
-    uint32_t* d_src_prefix = nullptr;             // [2][ns + 1]
-    uint32_t src_blocks[2] = {0, 0};
+    uint32_t* d_src_prefix = nullptr;             // per order and half step: ns_m + 1 block offsets
+    double* d_src_scal = nullptr;                 // 20 doubles per source: the half step's scalars
+    uint32_t src_first[3] = {0, 0, 0}, src_count[3] = {0, 0, 0};  // entries of order m = 1, 2, 3
+    size_t src_prefix_off[3][2] = {};
+    uint32_t src_blocks[3][2] = {};
     // graph of one full step
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -119,6 +122,7 @@ void free_batch(hermite_batch* b) {
     }
     if (b->d_srcs) (void)hipFree(b->d_srcs);
     if (b->d_src_prefix) (void)hipFree(b->d_src_prefix);
+    if (b->d_src_scal) (void)hipFree(b->d_src_scal);
     for (hipEvent_t& e : b->ev)
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t& s : b->cap)
@@ -167,10 +171,12 @@ int enqueue_full_step(hermite_batch* b, hipStream_t st, bool branches) {
         } else {
             for (const Group* g : act) BCHECK(b, launch_group(b, *g, g->choice, from, st), "batched half step");
         }
-        if (ns)
-            BCHECK(b, hermite::launch_source(b->d_srcs, b->d_src_prefix + from * (ns + 1), ns, b->src_blocks[from], from,
-                                             -1, st),
-                   "source launch");
+        for (int g = 0; g < 3; ++g)
+            if (b->src_count[g])
+                BCHECK(b, hermite::launch_source(b->d_srcs + b->src_first[g], b->d_src_prefix + b->src_prefix_off[g][from],
+                                                 b->src_count[g], b->src_blocks[g][from], g + 1, from, -1,
+                                                 b->d_src_scal + 20 * (size_t)b->src_first[g], st),
+                       "source launch");
     }
     if (ns) BCHECK(b, hermite::launch_advance_clock(b->d_srcs, ns, st), "clock launch");
     return HERMITE_OK;
@@ -375,32 +381,40 @@ int hermite_batch_create(int n_shots, const hermite_shot* shots, double cfl, dou
         if ((rc = upload(b, (unsigned char**)&g.K, Kdev, "upload operator")) != HERMITE_OK) return bail(rc);
     }
 
-    // sources
+    // sources, grouped by order (one source launch per order present)
     b->src_entry.assign(n_shots, -1);
-    for (int s = 0; s < n_shots; ++s) {
-        if (!shots[s].has_source || shots[s].source.amplitude == 0.0) continue;
-        hermite::SourceDesc d = hermite::make_source_desc(shots[s].source, shots[s].n_cells, shots[s].m,
-                                                          b->q[shots[s].m], cfl, c);
-        d.grid[0] = b->grids[s].grid[0];
-        d.grid[1] = b->grids[s].grid[1];
-        d.pitch = b->grids[s].pitch;
-        d.steps = 0;
-        b->src_entry[s] = (int)b->srcs.size();
-        b->srcs.push_back(d);
+    for (int m = 1; m <= 3; ++m) {
+        b->src_first[m - 1] = (uint32_t)b->srcs.size();
+        for (int s = 0; s < n_shots; ++s) {
+            if (shots[s].m != m || !shots[s].has_source || shots[s].source.amplitude == 0.0) continue;
+            hermite::SourceDesc d = hermite::make_source_desc(shots[s].source, shots[s].n_cells, m, b->q[m], cfl, c);
+            d.grid[0] = b->grids[s].grid[0];
+            d.grid[1] = b->grids[s].grid[1];
+            d.pitch = b->grids[s].pitch;
+            d.steps = 0;
+            b->src_entry[s] = (int)b->srcs.size();
+            b->srcs.push_back(d);
+        }
+        b->src_count[m - 1] = (uint32_t)b->srcs.size() - b->src_first[m - 1];
     }
     if (!b->srcs.empty()) {
-        const size_t ns = b->srcs.size();
-        std::vector<uint32_t> pre(2 * (ns + 1), 0);
-        for (int from = 0; from < 2; ++from) {
-            for (size_t i = 0; i < ns; ++i) {
-                const uint64_t next = (uint64_t)pre[from * (ns + 1) + i] + hermite::source_blocks(b->srcs[i], from);
-                if (next > 0x7FFFFFFFull) return bail(bfail(b, HERMITE_EINVAL, "sources exceed 2^31 blocks"));
-                pre[from * (ns + 1) + i + 1] = (uint32_t)next;
+        std::vector<uint32_t> pre;
+        for (int g = 0; g < 3; ++g)
+            for (int from = 0; from < 2; ++from) {
+                b->src_prefix_off[g][from] = pre.size();
+                pre.push_back(0);
+                for (uint32_t i = 0; i < b->src_count[g]; ++i) {
+                    const uint64_t next =
+                        (uint64_t)pre.back() + hermite::source_blocks(b->srcs[b->src_first[g] + i], from);
+                    if (next > 0x7FFFFFFFull) return bail(bfail(b, HERMITE_EINVAL, "sources exceed 2^31 blocks"));
+                    pre.push_back((uint32_t)next);
+                }
+                b->src_blocks[g][from] = pre.back();
             }
-            b->src_blocks[from] = pre[from * (ns + 1) + ns];
-        }
         int rc = upload(b, &b->d_srcs, b->srcs, "upload sources");
         if (rc == HERMITE_OK) rc = upload(b, &b->d_src_prefix, pre, "upload sources");
+        if (rc == HERMITE_OK) rc = upload(b, &b->d_src_scal, std::vector<double>(20 * b->srcs.size(), 0.0),
+                                          "allocate source scalars");
         if (rc) return bail(rc);
     }
 

@@ -31,6 +31,8 @@ struct hermite_ctx {
     int cus = 0;             // compute units of the device (persistent grids)
     int m3_kernel = 0;       // m = 3 fused FP64: 0 vector ALUs, 1 matrix cores
     int precision = 0;       // HERMITE_PREC_*: contraction arithmetic
+    int nf = 2;              // fields per node: 2 (wave: u, u_t) or 1 (advection)
+    std::vector<double> K1;  // advection: per-axis operator (M x 2M)
     double* grid[2] = {nullptr, nullptr};  // primal, dual: 2 M^3 columns of `pitch` doubles each
     double* R = nullptr;                   // two-kernel scratch: 2 P^3 columns of `pitch` doubles
     size_t ncell = 0;                      // n^3 nodes per column
@@ -43,6 +45,7 @@ struct hermite_ctx {
     bool has_source = false;
     hermite::SourceDesc* d_source = nullptr;  // one device entry
     uint32_t* d_source_prefix = nullptr;      // [from][2] block offsets
+    double* d_source_scal = nullptr;          // the half step's source scalars
     uint32_t source_blocks[2] = {0, 0};
     std::string err;
 };
@@ -81,6 +84,7 @@ void free_all(hermite_ctx* ctx) {
     if (ctx->Hp) { (void)hipFree(ctx->Hp); ctx->Hp = nullptr; }
     if (ctx->d_source) { (void)hipFree(ctx->d_source); ctx->d_source = nullptr; }
     if (ctx->d_source_prefix) { (void)hipFree(ctx->d_source_prefix); ctx->d_source_prefix = nullptr; }
+    if (ctx->d_source_scal) { (void)hipFree(ctx->d_source_scal); ctx->d_source_scal = nullptr; }
     if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
 }
 
@@ -96,7 +100,10 @@ int half_step(hermite_ctx* ctx, int from) {
     if (ctx->opt.poison)
         HCHECK(ctx, hipMemsetAsync(dst, 0xFF, ctx->grid_doubles * sizeof(double), ctx->stream), "poison");
     hipError_t e;
-    if (ctx->opt.fused) {
+    if (ctx->nf == 1) {
+        e = hermite::launch_advect(ctx->m, src, dst, ctx->K1.data(), ctx->n, ctx->pitch, off, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "advection half-step launch");
+    } else if (ctx->opt.fused) {
         const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
         if (ctx->precision != HERMITE_PREC_FP64) {
             e = hermite::launch_fused_mixed(ctx->precision, src, dst, ctx->K, ctx->n, ctx->pitch, off, grid,
@@ -118,8 +125,8 @@ int half_step(hermite_ctx* ctx, int from) {
         if (e != hipSuccess) return hip_fail(ctx, e, "evolution launch");
     }
     if (ctx->has_source) {
-        e = hermite::launch_source(ctx->d_source, ctx->d_source_prefix + 2 * from, 1, ctx->source_blocks[from], from,
-                                   ctx->steps, ctx->stream);
+        e = hermite::launch_source(ctx->d_source, ctx->d_source_prefix + 2 * from, 1, ctx->source_blocks[from], ctx->m,
+                                   from, ctx->steps, ctx->d_source_scal, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "source launch");
     }
     return HERMITE_OK;
@@ -161,14 +168,26 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     if (o.poison != 0 && o.poison != 1) return fail(nullptr, HERMITE_EINVAL, "poison=%d", o.poison);
     if (o.kernel < HERMITE_KERNEL_AUTO || o.kernel > HERMITE_KERNEL_VALU)
         return fail(nullptr, HERMITE_EINVAL, "kernel=%d", o.kernel);
+    if (o.equation != HERMITE_EQ_WAVE && o.equation != HERMITE_EQ_ADVECTION)
+        return fail(nullptr, HERMITE_EINVAL, "equation=%d", o.equation);
+    if (o.equation == HERMITE_EQ_ADVECTION) {
+        if (o.precision != HERMITE_PREC_FP64 || o.evolution != HERMITE_EVOLVE_TAYLOR || !o.fused)
+            return fail(nullptr, HERMITE_EUNSUPPORTED,
+                        "advection needs FP64, Taylor evolution and the fused kernel (precision=%d, evolution=%d, "
+                        "fused=%d)", o.precision, o.evolution, o.fused);
+        if (o.q != 0 && o.q < 3 * (2 * m + 1))
+            return fail(nullptr, HERMITE_EUNSUPPORTED, "advection needs q = 0 or q >= 3(2m+1) = %d (q=%d)",
+                        3 * (2 * m + 1), o.q);
+    }
     if (o.precision != HERMITE_PREC_FP64 && (m != 3 || !o.fused))
         return fail(nullptr, HERMITE_EUNSUPPORTED,
                     "precision=%d needs m = 3 and the fused kernel (m=%d, fused=%d)", o.precision, m, o.fused);
 
     const int M = m + 1, P = 2 * m + 2;
+    const int nf = (o.equation == HERMITE_EQ_ADVECTION) ? 1 : 2;
     const size_t nn = (size_t)n_cells * n_cells * n_cells;
     const size_t pitch = hermite::column_pitch(nn);
-    const size_t grid_doubles = (size_t)2 * M * M * M * pitch;
+    const size_t grid_doubles = (size_t)nf * M * M * M * pitch;
     const size_t r_doubles = o.fused ? 0 : (size_t)2 * P * P * P * pitch;
 
     hermite_ctx* ctx = new (std::nothrow) hermite_ctx();
@@ -183,7 +202,8 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     ctx->tau = 0.5 * ctx->dt;
     ctx->lam = c * ctx->tau / ctx->h;
     ctx->opt = o;
-    ctx->q = o.q ? o.q : 6 * m + 1;
+    ctx->nf = nf;
+    ctx->q = o.q ? o.q : (nf == 1 ? 3 * (2 * m + 1) : 6 * m + 1);
     ctx->substeps = o.rk_substeps ? o.rk_substeps : 1;
     ctx->grid_doubles = grid_doubles;
     ctx->ncell = nn;
@@ -223,7 +243,9 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     ctx->precision = o.precision;
     ctx->m3_kernel = (o.kernel == HERMITE_KERNEL_VALU) ? 0 : 1;
     std::vector<unsigned char> Kdev;
-    if (o.precision != HERMITE_PREC_FP64) {
+    if (nf == 1) {
+        ctx->K1 = hermite::advection_axis_operator(m, ctx->lam);
+    } else if (o.precision != HERMITE_PREC_FP64) {
         Kdev.resize(hermite::mixed_operator_bytes(o.precision));
         hermite::mixed_build_operators(o.precision, K.data(), Kdev.data());
     } else if (m == 3 && o.fused && ctx->m3_kernel == 1) {
@@ -236,10 +258,12 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         Kdev.resize(hermite::valu_small_operator_doubles(m) * sizeof(double));
         hermite::valu_small_build_operators(m, K.data(), (double*)Kdev.data());
     }
-    e = hipMalloc(&ctx->K, Kdev.size());
-    if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));
-    e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
+    if (!Kdev.empty()) {
+        e = hipMalloc(&ctx->K, Kdev.size());
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));
+        e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
+    }
     e = hipMalloc(&ctx->Hp, Hp.size() * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(Hp)"));
     e = hipMemcpy(ctx->Hp, Hp.data(), Hp.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -250,7 +274,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
 
 int hermite_set_initial(hermite_ctx* ctx, const double* u, const double* ut) {
     if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
-    if (!u || !ut) return fail(ctx, HERMITE_EINVAL, "u or ut is NULL");
+    if (!u || (!ut && ctx->nf == 2)) return fail(ctx, HERMITE_EINVAL, "u or ut is NULL");
     int rc = select_device(ctx);
     if (rc) return rc;
     const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), dp = ctx->pitch * sizeof(double);
@@ -258,9 +282,12 @@ int hermite_set_initial(hermite_ctx* ctx, const double* u, const double* ut) {
     double* gv = g + rows * ctx->pitch;
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_initial");
     HCHECK(ctx, hipMemcpy2D(g, dp, u, w, w, rows, hipMemcpyHostToDevice), "copy u");
-    HCHECK(ctx, hipMemcpy2D(gv, dp, ut, w, w, rows, hipMemcpyHostToDevice), "copy ut");
-    HCHECK(ctx, hermite::launch_scale(gv, ctx->pitch, gv, ctx->pitch, ctx->h / ctx->c, ctx->ncell, ctx->M3, ctx->stream),
-           "scale ut");
+    if (ctx->nf == 2) {
+        HCHECK(ctx, hipMemcpy2D(gv, dp, ut, w, w, rows, hipMemcpyHostToDevice), "copy ut");
+        HCHECK(ctx,
+               hermite::launch_scale(gv, ctx->pitch, gv, ctx->pitch, ctx->h / ctx->c, ctx->ncell, ctx->M3, ctx->stream),
+               "scale ut");
+    }
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "set_initial");
     ctx->has_state = true;
     ctx->steps = 0;
@@ -269,16 +296,17 @@ int hermite_set_initial(hermite_ctx* ctx, const double* u, const double* ut) {
 
 int hermite_set_initial_device(hermite_ctx* ctx, const void* u_dev, const void* ut_dev) {
     if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
-    if (!u_dev || !ut_dev) return fail(ctx, HERMITE_EINVAL, "u_dev or ut_dev is NULL");
+    if (!u_dev || (!ut_dev && ctx->nf == 2)) return fail(ctx, HERMITE_EINVAL, "u_dev or ut_dev is NULL");
     int rc = select_device(ctx);
     if (rc) return rc;
     const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), dp = ctx->pitch * sizeof(double);
     double* g = ctx->grid[0];
     double* gv = g + rows * ctx->pitch;
     HCHECK(ctx, hipMemcpy2DAsync(g, dp, u_dev, w, w, rows, hipMemcpyDeviceToDevice, ctx->stream), "copy u");
-    HCHECK(ctx, hermite::launch_scale(gv, ctx->pitch, (const double*)ut_dev, ctx->ncell, ctx->h / ctx->c, ctx->ncell,
-                                      ctx->M3, ctx->stream),
-           "scale ut");
+    if (ctx->nf == 2)
+        HCHECK(ctx, hermite::launch_scale(gv, ctx->pitch, (const double*)ut_dev, ctx->ncell, ctx->h / ctx->c,
+                                          ctx->ncell, ctx->M3, ctx->stream),
+               "scale ut");
     ctx->has_state = true;
     ctx->steps = 0;
     return HERMITE_OK;
@@ -308,7 +336,7 @@ int hermite_gather(hermite_ctx* ctx, double* u, double* ut, double* t_out) {
     const double* gv = g + rows * ctx->pitch;
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before gather (an earlier kernel failed)");
     if (u) HCHECK(ctx, hipMemcpy2D(u, w, g, sp, w, rows, hipMemcpyDeviceToHost), "copy u");
-    if (ut) {
+    if (ut && ctx->nf == 2) {
         // the dual grid is dead between full steps: use it as staging
         double* tmp = ctx->grid[1];
         HCHECK(ctx, hermite::launch_scale(tmp, ctx->pitch, gv, ctx->pitch, ctx->c / ctx->h, ctx->ncell, ctx->M3,
@@ -330,7 +358,7 @@ int hermite_gather_device(hermite_ctx* ctx, void* u_dev, void* ut_dev) {
     const double* g = ctx->grid[0];
     const double* gv = g + rows * ctx->pitch;
     if (u_dev) HCHECK(ctx, hipMemcpy2DAsync(u_dev, w, g, sp, w, rows, hipMemcpyDeviceToDevice, ctx->stream), "copy u");
-    if (ut_dev)
+    if (ut_dev && ctx->nf == 2)
         HCHECK(ctx, hermite::launch_scale((double*)ut_dev, ctx->ncell, gv, ctx->pitch, ctx->c / ctx->h, ctx->ncell,
                                           ctx->M3, ctx->stream),
                "scale ut");
@@ -345,8 +373,8 @@ int hermite_set_source(hermite_ctx* ctx, const hermite_source* src) {
     }
     const std::string why = hermite::check_source(*src);
     if (!why.empty()) return fail(ctx, HERMITE_EINVAL, "%s", why.c_str());
-    if (ctx->opt.evolution != HERMITE_EVOLVE_TAYLOR)
-        return fail(ctx, HERMITE_EUNSUPPORTED, "the point source needs Taylor evolution");
+    if (ctx->opt.evolution != HERMITE_EVOLVE_TAYLOR || ctx->nf != 2)
+        return fail(ctx, HERMITE_EUNSUPPORTED, "the point source needs the wave equation with Taylor evolution");
     int rc = select_device(ctx);
     if (rc) return rc;
     hermite::SourceDesc d = hermite::make_source_desc(*src, ctx->n, ctx->m, ctx->q, ctx->cfl, ctx->c);
@@ -358,6 +386,7 @@ int hermite_set_source(hermite_ctx* ctx, const hermite_source* src) {
     const uint32_t prefix[4] = {0, blocks[0], 0, blocks[1]};
     if (!ctx->d_source) HCHECK(ctx, hipMalloc(&ctx->d_source, sizeof(d)), "hipMalloc(source)");
     if (!ctx->d_source_prefix) HCHECK(ctx, hipMalloc(&ctx->d_source_prefix, sizeof(prefix)), "hipMalloc(source)");
+    if (!ctx->d_source_scal) HCHECK(ctx, hipMalloc(&ctx->d_source_scal, 20 * sizeof(double)), "hipMalloc(source)");
     // earlier half steps may still read the old entry
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_source");
     HCHECK(ctx, hipMemcpy(ctx->d_source, &d, sizeof(d), hipMemcpyHostToDevice), "upload source");

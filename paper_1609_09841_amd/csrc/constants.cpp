@@ -165,4 +165,18 @@ std::vector<double> fused_class_operators(int m, double lam, const std::vector<d
     return K;
 }
 
+std::vector<double> advection_axis_operator(int m, double lam) {
+    const int M = m + 1, P = 2 * m + 2;
+    const std::vector<double> H = hermite_matrix(m);
+    std::vector<double> K((size_t)M * P, 0.0);
+    for (int j = 0; j < M; ++j)
+        for (int a = 0; a < P; ++a) {
+            long double acc = 0.0L;
+            for (int k = j; k < P; ++k)
+                acc += binom(k, j) * std::pow((long double)lam, (long double)(k - j)) * (long double)H[(size_t)k * P + a];
+            K[(size_t)j * P + a] = (double)acc;
+        }
+    return K;
+}
+
 }  // namespace hermite

@@ -36,6 +36,12 @@ std::vector<double> evolution_poly(int m, int evolution, int q, int rk_substeps)
 // Layout [8][rows_max][2*M^3], rows_max = 2*nout(p=0)^3, unused rows zero.
 std::vector<double> fused_class_operators(int m, double lam, const std::vector<double>& cpoly);
 
+// Advection u_t = c (u_x1 + u_x2 + u_x3): with the exact stage count the
+// half step translates each cell polynomial by lam (1, 1, 1), lam = c tau/h,
+// so interpolation, evolution and truncation compose per axis into
+// K1 = T E H, M x P row-major, K1[j][a] = sum_k C(k, j) lam^(k-j) H[k][a].
+std::vector<double> advection_axis_operator(int m, double lam);
+
 int rows_max(int m);
 int nout(int M, int p);
 

@@ -71,10 +71,12 @@ struct SourceDesc {
 };
 // Blocks the source kernel needs for entry s in half step `from`.
 uint32_t source_blocks(const SourceDesc& s, int from);
-// srcs: ns device entries; prefix: ns + 1 device block offsets for this half
-// step (prefix[ns] = blocks). host_steps >= 0 replaces every entry's clock.
-hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_t ns, uint32_t blocks, int from,
-                         long long host_steps, hipStream_t st);
+// srcs: ns device entries, all of order m; prefix: ns + 1 device block
+// offsets for this half step (prefix[ns] = blocks). host_steps >= 0 replaces
+// every entry's clock. scal: device scratch of 20 ns doubles (the half
+// step's scalars, written and read within the call's two launches).
+hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_t ns, uint32_t blocks, int m, int from,
+                         long long host_steps, double* scal, hipStream_t st);
 // steps += 1 for every entry (end of a full step of a batch).
 hipError_t launch_advance_clock(SourceDesc* srcs, uint32_t ns, hipStream_t st);
 
@@ -97,6 +99,12 @@ hipError_t launch_fused_mfma_batch(const batch::ShotGrid* shots, const uint32_t*
 hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots, const uint32_t* ids,
                                     const uint32_t* prefix, uint32_t ng, int from, const void* Aops, int grid,
                                     uint32_t chunk, uint32_t interleaved, hipStream_t st);
+
+// Fused advection half step (m = 1..3, FP64): one field of M^3 columns per
+// grid; K1: advection_axis_operator (M x 2M doubles, host memory, passed by
+// value to the kernel).
+hipError_t launch_advect(int m, const double* src, double* dst, const double* K1, int n, size_t pitch, int off,
+                         hipStream_t st);
 
 // Interpolation half of the two-kernel variant: writes the monomial
 // coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity

@@ -19,11 +19,12 @@
 // new node of every cell within 6 sigma of the source (periodic nearest image
 // per axis; beyond 6 sigma along any axis g is taken as 0).
 //
-// One launch serves every source of a batch: blocks are dealt to sources by
-// a prefix table, and each block first forms its source's w_k, A_i and B_i
-// in LDS from the half step's start time, read from the source's device-side
-// step clock (so a captured graph replays with fixed arguments) or given by
-// the host.
+// Per half step two launches serve every source of one order m: a small
+// kernel forms each source's w_k, A_i and B_i from the half step's start
+// time, read from the source's device-side step clock (so a captured graph
+// replays with fixed arguments) or given by the host; then the main kernel,
+// whose blocks are dealt to the sources by a prefix table, runs one thread
+// per (box cell, j3).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -34,7 +35,6 @@
 namespace hermite {
 namespace {
 
-constexpr int kMaxP = 8;   // 2m + 2 for m <= 3
 constexpr int kMaxQ = 64;  // Taylor stages
 constexpr int kThreads = 256;
 
@@ -59,102 +59,156 @@ __device__ void ricker_series(double ta, double tau, double f0, double t0, int K
     }
 }
 
+// Scalars of one half step, out[e][0][i] = A_i i!, out[e][1][i] = B_i i!
+// (i <= 3m): one thread per (source e, i).
+__global__ void source_scalars_kernel(const SourceDesc* __restrict__ srcs, uint32_t ns, uint32_t from,
+                                      int64_t host_steps, double* __restrict__ out) {
+    const uint32_t e = blockIdx.x, i = threadIdx.x;
+    if (e >= ns) return;
+    const SourceDesc& S = srcs[e];
+    if (i > 3 * S.m) return;
+    const int q = (int)S.q;
+    const int64_t steps = host_steps >= 0 ? host_steps : S.steps;
+    double w[kMaxQ];
+    ricker_series((double)steps * S.dt + (from ? S.tau : 0.0), S.tau, S.f0, S.t0, q, w);
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k + 1 + 2 * (int)i <= q; ++k) {
+        double rb = 1.0;  // k! / (k + 1 + 2i)!
+        for (int l = k + 1; l <= k + 1 + 2 * (int)i; ++l) rb /= (double)l;
+        b += w[k] * rb;
+        if (k + 2 + 2 * (int)i <= q) a += w[k] * rb / (double)(k + 2 + 2 * i);
+    }
+    double l2i = 1.0, ifact = 1.0;  // lam^(2i), i!
+    for (uint32_t l = 1; l <= i; ++l) {
+        l2i *= S.lam * S.lam;
+        ifact *= (double)l;
+    }
+    out[(size_t)e * 20 + i] = S.pre * a * l2i * S.lam * ifact;
+    out[(size_t)e * 20 + 10 + i] = S.pre * b * l2i * ifact;
+}
+
+// Scaled Taylor coefficients g1[a], a < 2M, of the 1D Gaussian factor about
+// the cell centre `pos` (h^a/a! d^a/dx^a N(x; s, sigma) = N (-h/sigma)^a
+// He_a(z)/a!, z = d/sigma, d the nearest-image offset; 0 beyond 6 sigma).
+template <int M>
+__device__ __forceinline__ void gauss_coeffs(double pos, double s, double sigma, double h, double* g1) {
+    double d = pos - s;
+    d -= floor(d + 0.5);  // nearest periodic image, in [-1/2, 1/2)
+    if (fabs(d) > 6.0 * sigma) {
+#pragma unroll
+        for (int a = 0; a < 2 * M; ++a) g1[a] = 0.0;
+        return;
+    }
+    const double z = d / sigma;
+    const double base = exp(-0.5 * z * z) / (sigma * 2.5066282746310002);  // sqrt(2 pi)
+    const double r = -h / sigma;
+    double he_prev = 0.0, he = 1.0, hm = 1.0, fac = 1.0;
+#pragma unroll
+    for (int a = 0; a < 2 * M; ++a) {
+        g1[a] = base * hm * he / fac;
+        const double nxt = z * he - (double)a * he_prev;
+        he_prev = he;
+        he = nxt;
+        hm *= r;
+        fac *= (double)(a + 1);
+    }
+}
+
+// D[j][e] = (j + 2e)!/j! g1[j + 2e], e = 0 .. (2M-1-j)/2, for one axis.
+template <int M>
+__device__ __forceinline__ void axis_terms(const double* g1, int j, double* D) {
+    double ff = 1.0;
+#pragma unroll
+    for (int e = 0; e < M; ++e) {
+        if (j + 2 * e <= 2 * M - 1) {
+            if (e > 0) ff *= (double)((j + 2 * e - 1) * (j + 2 * e));
+            D[e] = ff * g1[j + 2 * e];
+        } else {
+            D[e] = 0.0;
+        }
+    }
+}
+
+// axis_terms for a runtime j (0 <= j < M), by compile-time selection so
+// that no array is indexed dynamically (which would put it in scratch).
+template <int M>
+__device__ __forceinline__ void axis_terms_rt(const double* g1, int j, double* D) {
+#pragma unroll
+    for (int e = 0; e < M; ++e) D[e] = 0.0;
+#pragma unroll
+    for (int jc = 0; jc < M; ++jc) {
+        double t[M];
+        axis_terms<M>(g1, jc, t);
+#pragma unroll
+        for (int e = 0; e < M; ++e) D[e] = (jc == j) ? t[e] : D[e];
+    }
+}
+
+// One thread per (box cell, j3): the M^2 outputs (j1, j2) of that j3, both
+// fields, P_j = sum_e i!/(e1! e2! e3!) [A_i | B_i] prod_x D_x(j_x, e_x),
+// i = |e|. AB: this source's scalars (A_i i!, B_i i!).
+template <int M>
 __global__ __launch_bounds__(kThreads) void source_kernel(const SourceDesc* __restrict__ srcs,
                                                           const uint32_t* __restrict__ prefix, uint32_t ns,
-                                                          uint32_t from, int64_t host_steps) {
-    __shared__ double sw[kMaxQ];
-    __shared__ double sAB[2][10];
+                                                          uint32_t from, const double* __restrict__ scal) {
     const uint32_t gi = batch::find_entry(prefix, ns, blockIdx.x);
     const SourceDesc& S = srcs[gi];
-    const int m = (int)S.m, M = m + 1, P = 2 * m + 2, M3 = M * M * M, q = (int)S.q;
-    const int64_t steps = host_steps >= 0 ? host_steps : S.steps;
-    if (threadIdx.x == 0) ricker_series((double)steps * S.dt + (from ? S.tau : 0.0), S.tau, S.f0, S.t0, q, sw);
-    __syncthreads();
-    if (threadIdx.x <= (unsigned)(3 * m)) {
-        const int i = (int)threadIdx.x;
-        double a = 0.0, b = 0.0;
-        for (int k = 0; k + 1 + 2 * i <= q; ++k) {
-            double rb = 1.0;  // k! / (k + 1 + 2i)!
-            for (int l = k + 1; l <= k + 1 + 2 * i; ++l) rb /= (double)l;
-            b += sw[k] * rb;
-            if (k + 2 + 2 * i <= q) a += sw[k] * rb / (double)(k + 2 + 2 * i);
-        }
-        double l2i = 1.0, ifact = 1.0;  // lam^(2i), i!
-        for (int l = 1; l <= i; ++l) {
-            l2i *= S.lam * S.lam;
-            ifact *= (double)l;
-        }
-        sAB[0][i] = S.pre * a * l2i * S.lam * ifact;  // A_i i!
-        sAB[1][i] = S.pre * b * l2i * ifact;          // B_i i!
-    }
-    __syncthreads();
-
     const uint32_t* box = S.box[from];
     const uint32_t n = S.n, nbx = box[3], nby = box[4], nbz = box[5];
     const uint64_t t = (uint64_t)(blockIdx.x - prefix[gi]) * kThreads + threadIdx.x;
-    const uint64_t nbox = (uint64_t)nbx * nby * nbz;
-    if (t >= nbox * (uint64_t)M3) return;
-    const uint64_t cellk = t / (uint64_t)M3;
-    const int jj = (int)(t % (uint64_t)M3);
-    const int j1 = jj % M, j2 = (jj / M) % M, j3 = jj / (M * M);
-    const uint32_t ib = (uint32_t)(cellk % nbx), jb = (uint32_t)((cellk / nbx) % nby),
-                   kb = (uint32_t)(cellk / ((uint64_t)nbx * nby));
+    if (t >= (uint64_t)nbx * nby * nbz * M) return;
+    const uint32_t cellk = (uint32_t)(t / M);  // box cells <= n^3 < 2^32
+    const int j3 = (int)(t % M);
+    const uint32_t ib = cellk % nbx, rest = cellk / nbx, jb = rest % nby, kb = rest / nby;
     const uint32_t i = (box[0] + ib) % n, j = (box[1] + jb) % n, k = (box[2] + kb) % n;
     // cell centre: lower corner + h/2 on the source grid (the dual grid sits
     // h/2 further along every axis)
     const double off_pos = from ? 0.5 : 0.0;
-    const double pos[3] = {((double)i + 0.5 + off_pos) * S.h, ((double)j + 0.5 + off_pos) * S.h,
-                           ((double)k + 0.5 + off_pos) * S.h};
-    const int jv[3] = {j1, j2, j3};
-    // per axis: D_x(e) = (j_x + 2e)!/j_x! * g1_x[j_x + 2e], e = 0 .. (2m+1-j_x)/2
-    double D[3][5];
-    int ne[3];
-    for (int x = 0; x < 3; ++x) {
-        double d = pos[x] - S.x[x];
-        d -= floor(d + 0.5);  // nearest periodic image, in [-1/2, 1/2)
-        const double z = d / S.sigma;
-        double g1[kMaxP];
-        if (fabs(d) > 6.0 * S.sigma) {
-            for (int a = 0; a < P; ++a) g1[a] = 0.0;
-        } else {
-            // g1_a = h^a/a! d^a/dx^a N(x; s, sigma) = N (-h/sigma)^a He_a(z)/a!
-            const double base = exp(-0.5 * z * z) / (S.sigma * 2.5066282746310002);  // sqrt(2 pi)
-            const double r = -S.h / S.sigma;
-            double he_prev = 0.0, he = 1.0, hm = 1.0, fac = 1.0;
-            for (int a = 0; a < P; ++a) {
-                g1[a] = base * hm * he / fac;
-                const double nxt = z * he - (double)a * he_prev;
-                he_prev = he;
-                he = nxt;
-                hm *= r;
-                fac *= (double)(a + 1);
-            }
-        }
-        ne[x] = (2 * m + 1 - jv[x]) / 2 + 1;
-        double ff = 1.0;  // (j + 2e)! / j!
-        for (int e = 0; e < ne[x]; ++e) {
-            if (e > 0) ff *= (double)((jv[x] + 2 * e - 1) * (jv[x] + 2 * e));
-            D[x][e] = ff * g1[jv[x] + 2 * e];
-        }
+    double g1[3][2 * M];
+    gauss_coeffs<M>(((double)i + 0.5 + off_pos) * S.h, S.x[0], S.sigma, S.h, g1[0]);
+    gauss_coeffs<M>(((double)j + 0.5 + off_pos) * S.h, S.x[1], S.sigma, S.h, g1[1]);
+    gauss_coeffs<M>(((double)k + 0.5 + off_pos) * S.h, S.x[2], S.sigma, S.h, g1[2]);
+    double D3[M];
+    axis_terms_rt<M>(g1[2], j3, D3);
+    const double* __restrict__ AB = scal + (size_t)gi * 20;
+    double A[3 * M - 2], Bv[3 * M - 2];
+#pragma unroll
+    for (int r = 0; r < 3 * M - 2; ++r) {
+        A[r] = AB[r];
+        Bv[r] = AB[10 + r];
     }
-    // sum_e i!/(e1! e2! e3!) [A_i | B_i] prod_x D_x(e_x), i = |e|
-    const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
-    double pu = 0.0, pv = 0.0;
-    for (int e3 = ne[2] - 1; e3 >= 0; --e3)
-        for (int e2 = ne[1] - 1; e2 >= 0; --e2)
-            for (int e1 = ne[0] - 1; e1 >= 0; --e1) {
-                const int ii = e1 + e2 + e3;
-                const double w = D[0][e1] * D[1][e2] * D[2][e3] * inv_fact[e1] * inv_fact[e2] * inv_fact[e3];
-                pu = fma(sAB[0][ii], w, pu);
-                pv = fma(sAB[1][ii], w, pv);
-            }
+    const double inv_fact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
     // the dual cell with lower corner (i, j, k) writes primal node (i+1, j+1, k+1)
     const uint32_t o = from ? 1u : 0u;
-    const uint32_t oi = (i + o) % n, oj = (j + o) % n, ok = (k + o) % n;
-    const size_t node = ((size_t)ok * n + oj) * n + oi;
+    const size_t node = ((size_t)((k + o) % n) * n + (j + o) % n) * n + (i + o) % n;
     double* __restrict__ dst = S.grid[1 - from];
-    dst[(size_t)jj * S.pitch + node] += S.amp * pu;
-    dst[(size_t)(M3 + jj) * S.pitch + node] += S.amp * pv;
+    constexpr int M3 = M * M * M;
+#pragma unroll
+    for (int j2 = 0; j2 < M; ++j2) {
+        double D2[M];
+        axis_terms<M>(g1[1], j2, D2);
+#pragma unroll
+        for (int j1 = 0; j1 < M; ++j1) {
+            double D1[M];
+            axis_terms<M>(g1[0], j1, D1);
+            double pu = 0.0, pv = 0.0;
+            // e_x <= (2M-1-j_x)/2: terms beyond degree 2M-1 are zero (for
+            // the runtime j3 the zero D3 entries do that)
+#pragma unroll
+            for (int e3 = M - 1; e3 >= 0; --e3)
+#pragma unroll
+                for (int e2 = (2 * M - 1 - j2) / 2; e2 >= 0; --e2)
+#pragma unroll
+                    for (int e1 = (2 * M - 1 - j1) / 2; e1 >= 0; --e1) {
+                        const double w = D1[e1] * D2[e2] * D3[e3] * (inv_fact[e1] * inv_fact[e2] * inv_fact[e3]);
+                        pu = fma(A[e1 + e2 + e3], w, pu);
+                        pv = fma(Bv[e1 + e2 + e3], w, pv);
+                    }
+            const int jj = (j3 * M + j2) * M + j1;
+            dst[(size_t)jj * S.pitch + node] += S.amp * pu;
+            dst[(size_t)(M3 + jj) * S.pitch + node] += S.amp * pv;
+        }
+    }
 }
 
 __global__ void advance_clock_kernel(SourceDesc* __restrict__ srcs, uint32_t ns) {
@@ -166,16 +220,21 @@ __global__ void advance_clock_kernel(SourceDesc* __restrict__ srcs, uint32_t ns)
 
 uint32_t source_blocks(const SourceDesc& s, int from) {
     const uint32_t* b = s.box[from];
-    const uint64_t M = s.m + 1;
-    const uint64_t total = (uint64_t)b[3] * b[4] * b[5] * M * M * M;
+    const uint64_t total = (uint64_t)b[3] * b[4] * b[5] * (s.m + 1);
     return (uint32_t)((total + kThreads - 1) / kThreads);
 }
 
-hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_t ns, uint32_t blocks, int from,
-                         long long host_steps, hipStream_t st) {
+hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_t ns, uint32_t blocks, int m, int from,
+                         long long host_steps, double* scal, hipStream_t st) {
     if (blocks == 0 || ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(source_kernel, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from,
-                       (int64_t)host_steps);
+    hipLaunchKernelGGL(source_scalars_kernel, dim3(ns), dim3(16), 0, st, srcs, ns, (uint32_t)from,
+                       (int64_t)host_steps, scal);
+    switch (m) {
+        case 1: hipLaunchKernelGGL(source_kernel<2>, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, (const double*)scal); break;
+        case 2: hipLaunchKernelGGL(source_kernel<3>, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, (const double*)scal); break;
+        case 3: hipLaunchKernelGGL(source_kernel<4>, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, (const double*)scal); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

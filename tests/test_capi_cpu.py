@@ -36,7 +36,8 @@ def test_options_struct_matches_header_field_order():
 
 def test_default_options():
     o = B.hermite_default_options()
-    assert (o.precision, o.evolution, o.rk_substeps, o.q, o.fused, o.poison, o.kernel) == (0, 0, 1, 0, 1, 0, 0)
+    assert (o.precision, o.evolution, o.rk_substeps, o.q, o.fused, o.poison, o.kernel, o.equation) == \
+        (0, 0, 1, 0, 1, 0, 0, 0)
     assert not o.stream
 
 
@@ -178,3 +179,19 @@ def test_valid_batch_create_without_device_reports_device_error():
     rc, h = B.hermite_batch_create([{"n": 8, "m": 1}, {"n": 6, "m": 3}], 0.5, 1.0)
     assert rc == B.HERMITE_EDEVICE and h is None
     assert B.hermite_batch_last_error(None) != ""
+
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("equation", 2, B.HERMITE_EINVAL),
+    ("precision", B.HERMITE_PREC_FP32, B.HERMITE_EUNSUPPORTED),
+    ("evolution", B.HERMITE_EVOLVE_RK4, B.HERMITE_EUNSUPPORTED),
+    ("fused", 0, B.HERMITE_EUNSUPPORTED),
+    ("q", 20, B.HERMITE_EUNSUPPORTED),   # below 3(2m+1) = 21 at m = 3
+])
+def test_advection_options_validated(field, value, code):
+    o = B.hermite_default_options()
+    o.equation = B.HERMITE_EQ_ADVECTION
+    setattr(o, field, value)
+    rc, h = B.hermite_create(8, 3, 0.5, 1.0, o)
+    assert rc == code and h is None
