@@ -711,3 +711,121 @@ int oracle_run_advection(int n, int m, real cfl, real c, int q, int nsteps, real
     free(b);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Adjoint (transpose) of the wave half step, for gradients of a misfit of
+ * receiver traces (an extension: the paper has no adjoint). A half step is
+ * linear: new = T E I G old (gather of the 8 vertices, interpolation,
+ * evolution polynomial, truncation to j <= m), so its transpose is
+ * G^T I^T E^T T^T: zero-pad the new node's data to the P^3 coefficients,
+ * apply E^T = sum_s c_s (L^T)^s with L^T(a, b) = lam (Lap^T b, a), apply H^T
+ * along each axis, and add the result into the 8 vertices. Each factor is
+ * the plain transposed loop of the forward step.
+ * ------------------------------------------------------------------------ */
+
+/* Lap^T: out[j + 2 e_x] += (j_x + 1)(j_x + 2) V[j], the transpose of the
+ * coefficient Laplacian of oracle_laplacian. */
+static void or_laplacian_T(int P, const real *V, real *out)
+{
+    const int n3 = P * P * P;
+    for (int t = 0; t < n3; ++t) out[t] = 0.0;
+    for (int j3 = 0; j3 < P; ++j3)
+        for (int j2 = 0; j2 < P; ++j2)
+            for (int j1 = 0; j1 < P; ++j1) {
+                const real v = V[(j3 * P + j2) * P + j1];
+                if (j1 + 2 < P) out[(j3 * P + j2) * P + j1 + 2] += (real)((j1 + 1) * (j1 + 2)) * v;
+                if (j2 + 2 < P) out[(j3 * P + j2 + 2) * P + j1] += (real)((j2 + 1) * (j2 + 2)) * v;
+                if (j3 + 2 < P) out[((j3 + 2) * P + j2) * P + j1] += (real)((j3 + 1) * (j3 + 2)) * v;
+            }
+}
+
+/* E^T of the q-stage Taylor evolution, by the Horner loop with L^T. */
+void oracle_evolve_taylor_T(int m, int q, real lam, real *Gu, real *Gv)
+{
+    const int P = 2 * m + 2, n3 = P * P * P;
+    real wu[OR_MAXP * OR_MAXP * OR_MAXP], wv[OR_MAXP * OR_MAXP * OR_MAXP], lt[OR_MAXP * OR_MAXP * OR_MAXP];
+    memcpy(wu, Gu, sizeof(real) * n3);
+    memcpy(wv, Gv, sizeof(real) * n3);
+    for (int k = q; k >= 1; --k) {
+        or_laplacian_T(P, wv, lt);  /* L^T (wu, wv) = lam (Lap^T wv, wu) */
+        for (int t = 0; t < n3; ++t) {
+            const real nu = Gu[t] + (lam / (real)k) * lt[t];
+            const real nv = Gv[t] + (lam / (real)k) * wu[t];
+            wu[t] = nu;
+            wv[t] = nv;
+        }
+    }
+    memcpy(Gu, wu, sizeof(real) * n3);
+    memcpy(Gv, wv, sizeof(real) * n3);
+}
+
+/* Transpose of oracle_interpolate_cell: H^T along x3, x2, x1. */
+void oracle_interpolate_cell_T(int m, const real *H, const real *R, real *uloc)
+{
+    const int P = 2 * m + 2;
+    real Ht[OR_MAXP * OR_MAXP], t1[OR_MAXP * OR_MAXP * OR_MAXP], t2[OR_MAXP * OR_MAXP * OR_MAXP];
+    for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) Ht[a * P + b] = H[b * P + a];
+    or_apply_axis(P, Ht, 2, R, t1);
+    or_apply_axis(P, Ht, 1, t1, t2);
+    or_apply_axis(P, Ht, 0, t2, uloc);
+}
+
+/* Transpose of one Taylor half step (oracle_half_step with evo = Taylor):
+ * lam_dst holds the adjoint of the destination grid (two fields), lam_src
+ * receives the adjoint of the source grid. Serial over cells (the
+ * scatter-add into shared vertices stays race-free and in a fixed order). */
+void oracle_adjoint_half_step(int n, int m, const real *H, real lam, int q, const real *lam_dst, real *lam_src,
+                              int to_dual)
+{
+    const int M = m + 1, P = 2 * M, M3 = M * M * M, n3 = P * P * P;
+    const long nn = (long)n * n * n;
+    const int off = to_dual ? 0 : 1;
+    for (long t = 0; t < 2 * (long)M3 * nn; ++t) lam_src[t] = 0.0;
+    real Gu[OR_MAXP * OR_MAXP * OR_MAXP], Gv[OR_MAXP * OR_MAXP * OR_MAXP];
+    real lu[OR_MAXP * OR_MAXP * OR_MAXP], lv[OR_MAXP * OR_MAXP * OR_MAXP];
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const long node = ((long)((k + off) % n) * n + (j + off) % n) * n + (i + off) % n;
+                for (int t = 0; t < n3; ++t) Gu[t] = Gv[t] = 0.0;
+                for (int d3 = 0; d3 < M; ++d3)
+                    for (int d2 = 0; d2 < M; ++d2)
+                        for (int d1 = 0; d1 < M; ++d1) {
+                            const int dd = (d3 * M + d2) * M + d1, jj = (d3 * P + d2) * P + d1;
+                            Gu[jj] = lam_dst[(long)dd * nn + node];
+                            Gv[jj] = lam_dst[(long)(M3 + dd) * nn + node];
+                        }
+                oracle_evolve_taylor_T(m, q, lam, Gu, Gv);
+                oracle_interpolate_cell_T(m, H, Gu, lu);
+                oracle_interpolate_cell_T(m, H, Gv, lv);
+                /* transpose of oracle_gather_cell: add into the 8 vertices */
+                for (int a3 = 0; a3 < P; ++a3)
+                    for (int a2 = 0; a2 < P; ++a2)
+                        for (int a1 = 0; a1 < P; ++a1) {
+                            const int s1 = a1 / M, d1 = a1 % M, s2 = a2 / M, d2 = a2 % M, s3 = a3 / M, d3 = a3 % M;
+                            const long vn = ((long)((k + s3) % n) * n + (j + s2) % n) * n + (i + s1) % n;
+                            const int dd = (d3 * M + d2) * M + d1, a = (a3 * P + a2) * P + a1;
+                            lam_src[(long)dd * nn + vn] += lu[a];
+                            lam_src[(long)(M3 + dd) * nn + vn] += lv[a];
+                        }
+            }
+}
+
+/* The source term of one half step alone: the forced half step applied to
+ * zero data (internal scaled variables, two fields, to the other grid). */
+int oracle_source_term(int n, int m, real cfl, real c, int q, int to_dual, real ta, const real *sx, real sigma,
+                       real f0, real t0, real amp, real *out)
+{
+    if (n < 1 || m < 1 || m > OR_MAXM || !(cfl > 0.0) || !(c > 0.0) || q < 1 || q > 64) return -1;
+    const int M = m + 1, M3 = M * M * M;
+    const long sz = 2 * (long)M3 * n * n * n;
+    const real h = 1.0 / (real)n, dt = cfl * h / c, tau = 0.5 * dt, lam = c * tau / h;
+    real H[OR_MAXP * OR_MAXP];
+    if (oracle_hermite_matrix(m, H) != 0) return -2;
+    real *zero = (real *)calloc((size_t)sz, sizeof(real));
+    if (!zero) return -3;
+    or_half_step_forced(n, m, H, lam, q, zero, out, to_dual, h, tau, c, ta, sx, sigma, f0, t0, amp);
+    free(zero);
+    return 0;
+}

@@ -29,6 +29,7 @@ __all__ = [
     "gather_cell", "half_step", "run", "point", "point_box", "exact_q",
     "gauss_taylor", "ricker_taylor", "evolve_taylor_forced", "run_forced",
     "advection_q", "evolve_advection", "run_advection",
+    "adjoint_half_step", "source_term", "run_series", "adjoint_series",
 ]
 
 
@@ -91,6 +92,14 @@ def load(ld: bool = False):
     lib.oracle_half_step_advection.restype = None
     lib.oracle_run_advection.argtypes = [i, i, d, d, i, i, dp]
     lib.oracle_run_advection.restype = i
+    lib.oracle_evolve_taylor_T.argtypes = [i, i, d, dp, dp]
+    lib.oracle_evolve_taylor_T.restype = None
+    lib.oracle_interpolate_cell_T.argtypes = [i, dp, dp, dp]
+    lib.oracle_interpolate_cell_T.restype = None
+    lib.oracle_adjoint_half_step.argtypes = [i, i, dp, d, i, dp, dp, i]
+    lib.oracle_adjoint_half_step.restype = None
+    lib.oracle_source_term.argtypes = [i, i, d, d, i, i, d, dp, d, d, d, d, dp]
+    lib.oracle_source_term.restype = i
     if ld:
         _lib_ld = lib
     else:
@@ -360,3 +369,85 @@ def run_advection(n: int, m: int, cfl: float, c: float, u, nsteps: int, q: int |
     if rc != 0:
         raise ValueError(f"oracle_run_advection failed: {rc}")
     return a.astype(np.float64).reshape(shape)
+
+
+# --- adjoint (gradients of receiver traces) ----------------------------------
+
+def adjoint_half_step(n: int, m: int, lam: float, lam_dst: np.ndarray, to_dual: bool, q: int | None = None):
+    """Transpose of half_step (Taylor, q stages) on internal variables
+    [2][M^3][n^3]: the adjoint of the source grid from that of the
+    destination grid."""
+    q = exact_q(m) if q is None else int(q)
+    H = hermite_matrix(m)
+    a = np.ascontiguousarray(lam_dst, dtype=np.float64)
+    out = np.zeros_like(a)
+    load().oracle_adjoint_half_step(n, m, _ptr(H), float(lam), q, _ptr(a), _ptr(out), int(bool(to_dual)))
+    return out
+
+
+def source_term(n: int, m: int, cfl: float, c: float, to_dual: bool, ta: float, source: dict,
+                q: int | None = None) -> np.ndarray:
+    """The point source's contribution to one half step starting at ta
+    (internal variables [2][M^3][n^3] on the destination grid)."""
+    q = exact_q(m) if q is None else int(q)
+    M3 = (m + 1) ** 3
+    out = np.zeros(2 * M3 * n ** 3)
+    sx = np.ascontiguousarray(np.asarray(source["x"], dtype=np.float64))
+    rc = load().oracle_source_term(n, m, float(cfl), float(c), q, int(bool(to_dual)), float(ta), _ptr(sx),
+                                   float(source["sigma"]), float(source["freq"]), float(source["t0"]),
+                                   float(source["amplitude"]), _ptr(out))
+    if rc != 0:
+        raise ValueError(rc)
+    return out
+
+
+def run_series(n: int, m: int, cfl: float, c: float, u0, ut0, nsteps: int, source: dict | None, amps,
+               receivers, q: int | None = None):
+    """Forward run whose source term in half step s (two per full step) is
+    multiplied by amps[s]; returns the traces [nsteps][R] of u at the primal
+    receiver nodes (i, j, k) after each full step, and the final (u, ut)."""
+    q = exact_q(m) if q is None else int(q)
+    M3 = (m + 1) ** 3
+    nn = n ** 3
+    h = 1.0 / n
+    dt = cfl * h / c
+    lam = c * 0.5 * dt / h
+    a = np.concatenate([np.asarray(u0, dtype=np.float64).ravel(), (h / c) * np.asarray(ut0, dtype=np.float64).ravel()])
+    rec = [(k * n + j) * n + i for (i, j, k) in receivers]
+    traces = np.zeros((nsteps, len(rec)))
+    for s in range(nsteps):
+        b = half_step(n, m, lam, a, True, "taylor", q)
+        if source is not None:
+            b += amps[2 * s] * source_term(n, m, cfl, c, True, s * dt, source, q)
+        a = half_step(n, m, lam, b, False, "taylor", q)
+        if source is not None:
+            a += amps[2 * s + 1] * source_term(n, m, cfl, c, False, s * dt + 0.5 * dt, source, q)
+        traces[s] = a[rec]
+    return traces, a[:M3 * nn].copy(), (c / h) * a[M3 * nn:]
+
+
+def adjoint_series(n: int, m: int, cfl: float, c: float, nsteps: int, source: dict | None, receivers, residual,
+                   q: int | None = None):
+    """Gradients of sum_{s, r} residual[s][r] traces[s][r] (traces of
+    run_series) with respect to u0, ut0 (flat [M^3 n^3]) and amps (2 nsteps):
+    the adjoint recursion run backwards with adjoint_half_step."""
+    q = exact_q(m) if q is None else int(q)
+    M3 = (m + 1) ** 3
+    nn = n ** 3
+    h = 1.0 / n
+    dt = cfl * h / c
+    lam = c * 0.5 * dt / h
+    rec = [(k * n + j) * n + i for (i, j, k) in receivers]
+    residual = np.asarray(residual, dtype=np.float64)
+    g = np.zeros(2 * M3 * nn)
+    gamps = np.zeros(2 * nsteps)
+    for s in range(nsteps - 1, -1, -1):
+        for r, node in enumerate(rec):
+            g[node] += residual[s, r]
+        if source is not None:
+            gamps[2 * s + 1] = g @ source_term(n, m, cfl, c, False, s * dt + 0.5 * dt, source, q)
+        mu = adjoint_half_step(n, m, lam, g, False, q)
+        if source is not None:
+            gamps[2 * s] = mu @ source_term(n, m, cfl, c, True, s * dt, source, q)
+        g = adjoint_half_step(n, m, lam, mu, True, q)
+    return g[:M3 * nn].copy(), (h / c) * g[M3 * nn:], gamps
