@@ -24,6 +24,9 @@ Also reported (outside the timed region of the headline):
     against the same shots run one after the other;
   * the paper's advection workload (Eq. 1): 150^3 cells, 200 steps, m = 1..3,
     time to solution next to the paper's (GTX 980, FP32: context only);
+  * gradient of a receiver misfit (96^3, m = 3, 200 steps, point source, 32
+    receivers) by the adjoint sweep, with a full-size central-difference
+    check;
   * the CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
@@ -102,6 +105,8 @@ def parse():
     ap.add_argument("--no-precision-study", action="store_true", help="skip the 256^3 precision study")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched point-source leg")
     ap.add_argument("--no-advection", action="store_true", help="skip the advection leg")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint-gradient leg")
+    ap.add_argument("--gradient-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96, help="grid of the oracle's timed sample")
@@ -287,6 +292,57 @@ def advection_leg(B, torch, I, n: int = 150, steps: int = 200, warmup: int = 1) 
     return out
 
 
+def gradient_leg(B, torch, I, n: int = 96, m: int = 3, steps: int = 200) -> dict:
+    """The differentiation workload: n^3 cells, order m, FP64, a Ricker point
+    source at the cube centre (sigma = 2h, f0 = c/(8h), t0 = 1.2/f0), 32
+    receivers on the plane z = 0.75, `steps` steps; misfit 1/2 |traces - obs|^2
+    against traces from a seeded perturbed initial u; gradient with respect to
+    u0, u_t0 and the per-half-step source amplitudes by the library's adjoint
+    sweep. Checked at full size by central differences in one direction."""
+    from paper_1609_09841_amd.autograd import receiver_traces
+    M = m + 1
+    f0 = n / 8.0
+    src = {"x": (0.5, 0.5, 0.5), "sigma": 2.0 / n, "freq": f0, "t0": 1.2 / f0, "amplitude": 1.0}
+    kz = int(round(0.75 * n))
+    rec = [((12 * a + 6) * n // 96, (24 * b + 12) * n // 96, kz) for a in range(8) for b in range(4)]
+    u0, ut0 = I.fourier_initial(n, m, device="cuda")
+    du, _ = I.fourier_initial(n, m, seed=1610, nmodes=4, kmax=4, device="cuda")
+    amps = torch.ones(2 * steps, dtype=torch.float64, device="cuda")
+    out = {"workload": f"{n}^3 cells, m={m}, FP64, Ricker source at the centre, 32 receivers on z=0.75, "
+                       f"{steps} steps, misfit against traces from u0 + 0.1 du (seeded)"}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream), B.Solver(n, m, 0.5, 1.0, stream=stream) as s:
+        s.set_receivers(rec)
+        s.set_source(src)
+        obs = receiver_traces(s, u0 + 0.1 * du, ut0, amps, steps).detach()
+        x = [u0.clone().requires_grad_(), ut0.clone().requires_grad_(), amps.clone().requires_grad_()]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = receiver_traces(s, *x, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = 0.5 * ((tr - obs) ** 2).sum()
+        grads = torch.autograd.grad(J, x)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        d = torch.randn(u0.shape, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+        eps = 1e-3
+        with torch.no_grad():
+            jp = 0.5 * ((receiver_traces(s, x[0] + eps * d, x[1], x[2], steps) - obs) ** 2).sum().item()
+            jm = 0.5 * ((receiver_traces(s, x[0] - eps * d, x[1], x[2], steps) - obs) ** 2).sum().item()
+        fd = (jp - jm) / (2 * eps)
+        ad = (grads[0] * d).sum().item()
+    dof = 2 * M ** 3 * n ** 3 * 2 * steps
+    out.update({"misfit": J.item(), "forward_s": t1 - t0, "adjoint_s": t2 - t1,
+                "forward_DOF_updates_per_s": dof / (t1 - t0), "adjoint_DOF_updates_per_s": dof / (t2 - t1),
+                "grad_norms": {"u0": grads[0].norm().item(), "ut0": grads[1].norm().item(),
+                               "amps": grads[2].norm().item()},
+                "central_difference_check": {"fd": fd, "adjoint": ad, "rel_err": abs(fd - ad) / abs(ad)}})
+    del u0, ut0, du, x, grads, tr, obs, d
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(m: int, n_s: int) -> dict:
     """The oracle (plain FP64 C, OpenMP) on a bounded sample of the workload:
     the same data recipe and order on an n_s^3 grid, one full step."""
@@ -394,6 +450,8 @@ def main():
         out["advection"] = advection_leg(B, torch, I)
     if not args.no_batch:
         out["batch"] = batch_leg(B, torch, I, steps=args.batch_steps)
+    if not args.no_gradient:
+        out["gradient"] = gradient_leg(B, torch, I, steps=args.gradient_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_n)
     print(json.dumps(out), flush=True)

@@ -180,6 +180,52 @@ typedef struct hermite_source {
 
 int hermite_set_source(hermite_ctx *ctx, const hermite_source *src);
 
+/* ------------------------------------------------------------------------
+ * Receivers and gradients (adjoint sweep). An extension: the paper has no
+ * adjoint. For the wave equation in FP64 (HERMITE_EUNSUPPORTED otherwise).
+ * ------------------------------------------------------------------------ */
+
+/* Receivers at primal nodes ijk[r] = (i, j, k), 0 <= i, j, k < n (host
+ * array of 3 n_rec ints, copied); they record u (the value, d = 0).
+ * n_rec = 0 removes them. */
+int hermite_set_receivers(hermite_ctx *ctx, int n_rec, const int *ijk);
+
+/* Scales the point source of half step h (two per full step, counted from
+ * t = 0) by amps_dev[h], h < n_half (device array of doubles, read by the
+ * kernels at each half step: the caller keeps it alive and unchanged while
+ * steps are enqueued). Needs a source (HERMITE_ESTATE). NULL removes the
+ * scaling. hermite_step fails with HERMITE_EINVAL for half steps beyond
+ * n_half. */
+int hermite_set_source_series(hermite_ctx *ctx, const void *amps_dev, long long n_half);
+
+/* As hermite_step, and after each full step s writes the receivers' u to
+ * traces_dev[s * n_rec + r] (device doubles). Needs receivers. */
+int hermite_step_record(hermite_ctx *ctx, int n_full_steps, void *traces_dev);
+
+/* Starts an adjoint sweep at the context's current time t = steps * dt:
+ * the adjoint state (the gradient of the objective with respect to the state
+ * u, u_t at t) is set from device arrays lam_u_dev, lam_ut_dev (layout of
+ * hermite_set_initial), or zero when both are NULL. The forward state is
+ * replaced (hermite_set_initial is needed before stepping again). */
+int hermite_adjoint_init(hermite_ctx *ctx, const void *lam_u_dev, const void *lam_ut_dev);
+
+/* n_full_steps steps of the adjoint sweep, back in time. res_dev (device,
+ * n_full_steps * n_rec doubles, may be NULL without receivers): res[s][r] is
+ * the derivative of the objective with respect to the trace value that
+ * hermite_step_record wrote after full step t0 + s, t0 = (sweep time in
+ * steps) - n_full_steps; it is added into the adjoint state at that step.
+ * grad_amps_dev (device, 2 n_full_steps doubles, or NULL): receives the
+ * derivative with respect to the source scaling of half steps 2 t0 .. 2 t0 +
+ * 2 n_full_steps - 1 (needs a source). Each step applies the transposes of
+ * the two half steps (the transpose of a fused half step: its class
+ * operators transposed and the vertex butterfly reversed, gathered per node
+ * over the 8 cells around it). */
+int hermite_adjoint_step(hermite_ctx *ctx, int n_full_steps, const void *res_dev, void *grad_amps_dev);
+
+/* Copies the adjoint state, i.e. the gradient with respect to u and u_t at
+ * the sweep's current time, to device arrays (either may be NULL). */
+int hermite_adjoint_gather(hermite_ctx *ctx, void *gu_dev, void *gut_dev);
+
 /* Waits for all work enqueued on the context's stream. */
 int hermite_sync(hermite_ctx *ctx);
 

@@ -44,7 +44,8 @@ EXPORTS = (
     "hermite_destroy", "hermite_last_error", "hermite_set_source",
     "hermite_batch_default_options", "hermite_batch_create", "hermite_batch_set_initial", "hermite_batch_step",
     "hermite_batch_gather", "hermite_batch_sync", "hermite_batch_tuning", "hermite_batch_destroy",
-    "hermite_batch_last_error",
+    "hermite_batch_last_error", "hermite_set_receivers", "hermite_set_source_series", "hermite_step_record",
+    "hermite_adjoint_init", "hermite_adjoint_step", "hermite_adjoint_gather",
 )
 
 
@@ -137,6 +138,18 @@ def load(path: str = LIB_PATH):
     lib.hermite_set_source.restype = ip
     lib.hermite_last_error.argtypes = [vp]
     lib.hermite_last_error.restype = ctypes.c_char_p
+    lib.hermite_set_receivers.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.hermite_set_receivers.restype = ip
+    lib.hermite_set_source_series.argtypes = [vp, vp, ctypes.c_longlong]
+    lib.hermite_set_source_series.restype = ip
+    lib.hermite_step_record.argtypes = [vp, ip, vp]
+    lib.hermite_step_record.restype = ip
+    lib.hermite_adjoint_init.argtypes = [vp, vp, vp]
+    lib.hermite_adjoint_init.restype = ip
+    lib.hermite_adjoint_step.argtypes = [vp, ip, vp, vp]
+    lib.hermite_adjoint_step.restype = ip
+    lib.hermite_adjoint_gather.argtypes = [vp, vp, vp]
+    lib.hermite_adjoint_gather.restype = ip
     bopt_p = ctypes.POINTER(hermite_batch_options)
     lib.hermite_batch_default_options.argtypes = [bopt_p]
     lib.hermite_batch_default_options.restype = None
@@ -264,6 +277,45 @@ class Solver:
 
     def step(self, nsteps: int = 1):
         _check(self._lib.hermite_step(self._ctx, int(nsteps)), self._ctx)
+
+    # --- receivers and the adjoint sweep (device arrays are torch tensors) ---
+
+    def set_receivers(self, ijk):
+        """Primal receiver nodes [(i, j, k), ...]; [] removes them."""
+        arr = (ctypes.c_int * (3 * len(ijk)))(*[int(v) for p in ijk for v in p])
+        _check(self._lib.hermite_set_receivers(self._ctx, len(ijk), arr), self._ctx)
+        self.nrec = len(ijk)
+
+    def set_source_series(self, amps):
+        """Scale the source of half step h by amps[h] (CUDA float64 tensor kept
+        alive by this object); None removes the scaling."""
+        if amps is None:
+            _check(self._lib.hermite_set_source_series(self._ctx, None, 0), self._ctx)
+            self._amps = None
+            return
+        assert amps.is_cuda and str(amps.dtype) == "torch.float64" and amps.is_contiguous()
+        self._amps = amps
+        _check(self._lib.hermite_set_source_series(self._ctx, ctypes.c_void_p(amps.data_ptr()), amps.numel()),
+               self._ctx)
+
+    def step_record(self, nsteps: int, traces):
+        assert traces.is_cuda and traces.is_contiguous() and traces.numel() == nsteps * self.nrec
+        _check(self._lib.hermite_step_record(self._ctx, int(nsteps), ctypes.c_void_p(traces.data_ptr())), self._ctx)
+
+    def adjoint_init(self, lam_u=None, lam_ut=None):
+        a = ctypes.c_void_p(lam_u.data_ptr()) if lam_u is not None else None
+        b = ctypes.c_void_p(lam_ut.data_ptr()) if lam_ut is not None else None
+        _check(self._lib.hermite_adjoint_init(self._ctx, a, b), self._ctx)
+
+    def adjoint_step(self, nsteps: int, res=None, grad_amps=None):
+        a = ctypes.c_void_p(res.data_ptr()) if res is not None else None
+        b = ctypes.c_void_p(grad_amps.data_ptr()) if grad_amps is not None else None
+        _check(self._lib.hermite_adjoint_step(self._ctx, int(nsteps), a, b), self._ctx)
+
+    def adjoint_gather(self, gu=None, gut=None):
+        a = ctypes.c_void_p(gu.data_ptr()) if gu is not None else None
+        b = ctypes.c_void_p(gut.data_ptr()) if gut is not None else None
+        _check(self._lib.hermite_adjoint_gather(self._ctx, a, b), self._ctx)
 
     def sync(self):
         _check(self._lib.hermite_sync(self._ctx), self._ctx)

@@ -6,6 +6,7 @@
 // (Sec. 2), on the context's stream; nothing waits on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -47,6 +48,15 @@ struct hermite_ctx {
     uint32_t* d_source_prefix = nullptr;      // [from][2] block offsets
     double* d_source_scal = nullptr;          // the half step's source scalars
     uint32_t source_blocks[2] = {0, 0};
+    hermite::SourceDesc source_desc{};        // host copy of the device entry
+    long long series_len = 0;                 // amplitude series length (half steps), 0 = none
+    uint32_t* d_rec = nullptr;                // receiver nodes (flat primal indices)
+    uint32_t nrec = 0;
+    void* Kadj = nullptr;                     // canonical class operators (adjoint kernel)
+    double* d_partial = nullptr;              // source-gradient block partials
+    uint32_t partial_cap = 0;                 // doubles in d_partial
+    bool adjoint = false;                     // grids hold an adjoint state
+    long long adj_steps = 0;                  // the adjoint sweep's time, in full steps
     std::string err;
 };
 
@@ -85,6 +95,9 @@ void free_all(hermite_ctx* ctx) {
     if (ctx->d_source) { (void)hipFree(ctx->d_source); ctx->d_source = nullptr; }
     if (ctx->d_source_prefix) { (void)hipFree(ctx->d_source_prefix); ctx->d_source_prefix = nullptr; }
     if (ctx->d_source_scal) { (void)hipFree(ctx->d_source_scal); ctx->d_source_scal = nullptr; }
+    if (ctx->d_rec) { (void)hipFree(ctx->d_rec); ctx->d_rec = nullptr; }
+    if (ctx->Kadj) { (void)hipFree(ctx->Kadj); ctx->Kadj = nullptr; }
+    if (ctx->d_partial) { (void)hipFree(ctx->d_partial); ctx->d_partial = nullptr; }
     if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
 }
 
@@ -291,6 +304,7 @@ int hermite_set_initial(hermite_ctx* ctx, const double* u, const double* ut) {
     HCHECK(ctx, hipStreamSynchronize(ctx->stream), "set_initial");
     ctx->has_state = true;
     ctx->steps = 0;
+    ctx->adjoint = false;
     return HERMITE_OK;
 }
 
@@ -309,6 +323,7 @@ int hermite_set_initial_device(hermite_ctx* ctx, const void* u_dev, const void* 
                "scale ut");
     ctx->has_state = true;
     ctx->steps = 0;
+    ctx->adjoint = false;
     return HERMITE_OK;
 }
 
@@ -316,6 +331,9 @@ int hermite_step(hermite_ctx* ctx, int n_full_steps) {
     if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
     if (n_full_steps < 0) return fail(ctx, HERMITE_EINVAL, "n_full_steps=%d < 0", n_full_steps);
     if (!ctx->has_state) return fail(ctx, HERMITE_ESTATE, "hermite_step before hermite_set_initial");
+    if (ctx->has_source && ctx->source_desc.series && 2 * (ctx->steps + n_full_steps) > ctx->series_len)
+        return fail(ctx, HERMITE_EINVAL, "the source amplitude series (%lld half steps) ends before step %lld",
+                    ctx->series_len, ctx->steps + n_full_steps);
     int rc = select_device(ctx);
     if (rc) return rc;
     for (int s = 0; s < n_full_steps; ++s) {
@@ -323,6 +341,21 @@ int hermite_step(hermite_ctx* ctx, int n_full_steps) {
         if ((rc = half_step(ctx, 1)) != HERMITE_OK) return rc;
         ++ctx->steps;
     }
+    return HERMITE_OK;
+}
+
+int hermite_step_record(hermite_ctx* ctx, int n_full_steps, void* traces_dev) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (ctx->nrec == 0) return fail(ctx, HERMITE_ESTATE, "hermite_step_record without receivers");
+    if (!traces_dev && n_full_steps > 0) return fail(ctx, HERMITE_EINVAL, "traces_dev is NULL");
+    for (int s = 0; s < n_full_steps; ++s) {
+        const int rc = hermite_step(ctx, 1);
+        if (rc) return rc;
+        HCHECK(ctx, hermite::launch_record(ctx->grid[0], ctx->d_rec, ctx->nrec, (double*)traces_dev + (size_t)s * ctx->nrec,
+                                           ctx->stream),
+               "record launch");
+    }
+    if (n_full_steps == 0) return hermite_step(ctx, 0);
     return HERMITE_OK;
 }
 
@@ -382,6 +415,7 @@ int hermite_set_source(hermite_ctx* ctx, const hermite_source* src) {
     d.grid[1] = ctx->grid[1];
     d.pitch = ctx->pitch;
     d.steps = 0;  // unused: the host passes the step count at each launch
+    d.series = nullptr;  // a new source starts without an amplitude series
     const uint32_t blocks[2] = {hermite::source_blocks(d, 0), hermite::source_blocks(d, 1)};
     const uint32_t prefix[4] = {0, blocks[0], 0, blocks[1]};
     if (!ctx->d_source) HCHECK(ctx, hipMalloc(&ctx->d_source, sizeof(d)), "hipMalloc(source)");
@@ -393,7 +427,161 @@ int hermite_set_source(hermite_ctx* ctx, const hermite_source* src) {
     HCHECK(ctx, hipMemcpy(ctx->d_source_prefix, prefix, sizeof(prefix), hipMemcpyHostToDevice), "upload source");
     ctx->source_blocks[0] = blocks[0];
     ctx->source_blocks[1] = blocks[1];
+    ctx->source_desc = d;
+    ctx->series_len = 0;
     ctx->has_source = true;
+    return HERMITE_OK;
+}
+
+int hermite_set_source_series(hermite_ctx* ctx, const void* amps_dev, long long n_half) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!ctx->has_source) return fail(ctx, HERMITE_ESTATE, "hermite_set_source_series without a source");
+    if (amps_dev && n_half < 0) return fail(ctx, HERMITE_EINVAL, "n_half=%lld < 0", n_half);
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    hermite::SourceDesc d = ctx->source_desc;
+    d.series = amps_dev ? (const double*)amps_dev : nullptr;
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_source_series");
+    HCHECK(ctx, hipMemcpy(ctx->d_source, &d, sizeof(d), hipMemcpyHostToDevice), "upload source");
+    ctx->source_desc = d;
+    ctx->series_len = amps_dev ? n_half : 0;
+    return HERMITE_OK;
+}
+
+int hermite_set_receivers(hermite_ctx* ctx, int n_rec, const int* ijk) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (n_rec < 0 || n_rec > (1 << 24)) return fail(ctx, HERMITE_EINVAL, "n_rec=%d", n_rec);
+    if (n_rec > 0 && !ijk) return fail(ctx, HERMITE_EINVAL, "ijk is NULL");
+    std::vector<uint32_t> nodes((size_t)n_rec);
+    for (int r = 0; r < n_rec; ++r) {
+        const int i = ijk[3 * r], j = ijk[3 * r + 1], k = ijk[3 * r + 2];
+        if (i < 0 || j < 0 || k < 0 || i >= ctx->n || j >= ctx->n || k >= ctx->n)
+            return fail(ctx, HERMITE_EINVAL, "receiver %d at (%d, %d, %d) outside the grid", r, i, j, k);
+        nodes[r] = (uint32_t)(((size_t)k * ctx->n + j) * ctx->n + i);
+    }
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before set_receivers");
+    if (ctx->d_rec) {
+        (void)hipFree(ctx->d_rec);
+        ctx->d_rec = nullptr;
+        ctx->nrec = 0;
+    }
+    if (n_rec > 0) {
+        HCHECK(ctx, hipMalloc(&ctx->d_rec, nodes.size() * sizeof(uint32_t)), "hipMalloc(receivers)");
+        HCHECK(ctx, hipMemcpy(ctx->d_rec, nodes.data(), nodes.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+               "upload receivers");
+    }
+    ctx->nrec = (uint32_t)n_rec;
+    return HERMITE_OK;
+}
+
+namespace {
+
+int adjoint_supported(hermite_ctx* ctx) {
+    if (ctx->nf != 2 || ctx->precision != HERMITE_PREC_FP64)
+        return fail(ctx, HERMITE_EUNSUPPORTED, "the adjoint needs the wave equation in FP64");
+    return HERMITE_OK;
+}
+
+}  // namespace
+
+int hermite_adjoint_init(hermite_ctx* ctx, const void* lam_u_dev, const void* lam_ut_dev) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    int rc = adjoint_supported(ctx);
+    if (rc) return rc;
+    if (!ctx->has_state && !ctx->adjoint) return fail(ctx, HERMITE_ESTATE, "hermite_adjoint_init before a forward run");
+    if ((lam_u_dev == nullptr) != (lam_ut_dev == nullptr))
+        return fail(ctx, HERMITE_EINVAL, "lam_u_dev and lam_ut_dev must both be given or both NULL");
+    if ((rc = select_device(ctx)) != HERMITE_OK) return rc;
+    if (!ctx->Kadj) {
+        const std::vector<double> cpoly = hermite::evolution_poly(ctx->m, ctx->opt.evolution, ctx->q, ctx->substeps);
+        const std::vector<double> K = hermite::fused_class_operators(ctx->m, ctx->lam, cpoly);
+        HCHECK(ctx, hipMalloc(&ctx->Kadj, K.size() * sizeof(double)), "hipMalloc(adjoint operator)");
+        HCHECK(ctx, hipMemcpy(ctx->Kadj, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice),
+               "upload adjoint operator");
+    }
+    const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), dp = ctx->pitch * sizeof(double);
+    double* g = ctx->grid[0];
+    double* gv = g + rows * ctx->pitch;
+    if (lam_u_dev) {
+        // d/d(vt) = (c/h) d/d(u_t), since u_t = (c/h) vt
+        HCHECK(ctx, hipMemcpy2DAsync(g, dp, lam_u_dev, w, w, rows, hipMemcpyDeviceToDevice, ctx->stream), "copy lam_u");
+        HCHECK(ctx, hermite::launch_scale(gv, ctx->pitch, (const double*)lam_ut_dev, ctx->ncell, ctx->c / ctx->h,
+                                          ctx->ncell, ctx->M3, ctx->stream),
+               "scale lam_ut");
+    } else {
+        HCHECK(ctx, hipMemsetAsync(g, 0, ctx->grid_doubles * sizeof(double), ctx->stream), "zero adjoint");
+    }
+    ctx->adj_steps = ctx->adjoint ? ctx->adj_steps : ctx->steps;
+    ctx->adjoint = true;
+    ctx->has_state = false;
+    return HERMITE_OK;
+}
+
+int hermite_adjoint_step(hermite_ctx* ctx, int n_full_steps, const void* res_dev, void* grad_amps_dev) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!ctx->adjoint) return fail(ctx, HERMITE_ESTATE, "hermite_adjoint_step before hermite_adjoint_init");
+    if (n_full_steps < 0 || n_full_steps > ctx->adj_steps)
+        return fail(ctx, HERMITE_EINVAL, "n_full_steps=%d outside [0, %lld]", n_full_steps, ctx->adj_steps);
+    if (ctx->nrec > 0 && !res_dev && n_full_steps > 0) return fail(ctx, HERMITE_EINVAL, "res_dev is NULL");
+    if (grad_amps_dev && !ctx->has_source)
+        return fail(ctx, HERMITE_ESTATE, "grad_amps_dev given without a source");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    const uint32_t need = std::max<uint32_t>(1, std::max(ctx->source_blocks[0], ctx->source_blocks[1]));
+    if (grad_amps_dev && ctx->partial_cap < need) {
+        HCHECK(ctx, hipStreamSynchronize(ctx->stream), "sync before reallocating partials");
+        if (ctx->d_partial) (void)hipFree(ctx->d_partial);
+        ctx->d_partial = nullptr;
+        ctx->partial_cap = 0;
+        HCHECK(ctx, hipMalloc(&ctx->d_partial, need * sizeof(double)), "hipMalloc(partials)");
+        ctx->partial_cap = need;
+    }
+    const long long t0 = ctx->adj_steps - n_full_steps;
+    double* lam_p = ctx->grid[0];
+    double* lam_d = ctx->grid[1];
+    for (int s = n_full_steps - 1; s >= 0; --s) {
+        const long long k = t0 + s;  // the full step being reversed
+        if (ctx->nrec > 0)
+            HCHECK(ctx, hermite::launch_inject(lam_p, ctx->d_rec, ctx->nrec, (const double*)res_dev + (size_t)s * ctx->nrec,
+                                               ctx->stream),
+                   "inject launch");
+        if (grad_amps_dev)
+            HCHECK(ctx, hermite::launch_source_dot(ctx->d_source, ctx->d_source_prefix + 2, ctx->source_blocks[1], ctx->m,
+                                                   1, k, ctx->d_source_scal, ctx->d_partial,
+                                                   (double*)grad_amps_dev + 2 * s + 1, ctx->stream),
+                   "source gradient launch");
+        HCHECK(ctx, hermite::launch_adjoint(ctx->m, lam_p, lam_d, (const double*)ctx->Kadj, ctx->n, ctx->pitch, 1,
+                                            ctx->stream),
+               "adjoint half-step launch");
+        if (grad_amps_dev)
+            HCHECK(ctx, hermite::launch_source_dot(ctx->d_source, ctx->d_source_prefix, ctx->source_blocks[0], ctx->m, 0,
+                                                   k, ctx->d_source_scal, ctx->d_partial,
+                                                   (double*)grad_amps_dev + 2 * s, ctx->stream),
+                   "source gradient launch");
+        HCHECK(ctx, hermite::launch_adjoint(ctx->m, lam_d, lam_p, (const double*)ctx->Kadj, ctx->n, ctx->pitch, 0,
+                                            ctx->stream),
+               "adjoint half-step launch");
+    }
+    ctx->adj_steps = t0;
+    return HERMITE_OK;
+}
+
+int hermite_adjoint_gather(hermite_ctx* ctx, void* gu_dev, void* gut_dev) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!ctx->adjoint) return fail(ctx, HERMITE_ESTATE, "hermite_adjoint_gather before hermite_adjoint_init");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), sp = ctx->pitch * sizeof(double);
+    const double* g = ctx->grid[0];
+    const double* gv = g + rows * ctx->pitch;
+    if (gu_dev) HCHECK(ctx, hipMemcpy2DAsync(gu_dev, w, g, sp, w, rows, hipMemcpyDeviceToDevice, ctx->stream), "copy gu");
+    // d/d(u_t) = (h/c) d/d(vt)
+    if (gut_dev)
+        HCHECK(ctx, hermite::launch_scale((double*)gut_dev, ctx->ncell, gv, ctx->pitch, ctx->h / ctx->c, ctx->ncell,
+                                          ctx->M3, ctx->stream),
+               "scale gut");
     return HERMITE_OK;
 }
 

@@ -68,6 +68,7 @@ struct SourceDesc {
     double sigma, amp, f0, t0;
     double h, tau, dt, lam, pre;  // pre = tau h / c
     int64_t steps;       // full steps taken: the device-side clock
+    const double* series;  // NULL, or the amplitude of half step 2 steps + from
 };
 // Blocks the source kernel needs for entry s in half step `from`.
 uint32_t source_blocks(const SourceDesc& s, int from);
@@ -77,6 +78,23 @@ uint32_t source_blocks(const SourceDesc& s, int from);
 // step's scalars, written and read within the call's two launches).
 hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_t ns, uint32_t blocks, int m, int from,
                          long long host_steps, double* scal, hipStream_t st);
+// Gradient of an amplitude series entry: *grad = <lam, P> over the
+// destination grid grid[1 - from] (which holds the adjoint lam) for one
+// source entry, P its source term of the half step with unit amplitude
+// series (times the entry's amp). partial: device scratch of `blocks`
+// doubles; the sum runs in a fixed order.
+hipError_t launch_source_dot(const SourceDesc* src, const uint32_t* prefix, uint32_t blocks, int m, int from,
+                             long long host_steps, double* scal, double* partial, double* grad, hipStream_t st);
+
+// Transposed fused half step (FP64): lam_src (adjoint of the grid the half
+// step reads) from lam_dst (adjoint of the grid it writes); K: canonical
+// class operators ([8][rows_max][2 M^3], fused_class_operators), device.
+hipError_t launch_adjoint(int m, const double* lam_dst, double* lam_src, const double* K, int n, size_t pitch, int off,
+                          hipStream_t st);
+// Receivers: traces[r] = grid[nodes[r]] (u, d = 0 of the primal grid);
+// inject: lam[nodes[r]] += res[r] in receiver order.
+hipError_t launch_record(const double* grid, const uint32_t* nodes, uint32_t nr, double* traces, hipStream_t st);
+hipError_t launch_inject(double* lam, const uint32_t* nodes, uint32_t nr, const double* res, hipStream_t st);
 // steps += 1 for every entry (end of a full step of a batch).
 hipError_t launch_advance_clock(SourceDesc* srcs, uint32_t ns, hipStream_t st);
 

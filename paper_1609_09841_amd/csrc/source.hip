@@ -61,8 +61,9 @@ __device__ void ricker_series(double ta, double tau, double f0, double t0, int K
 
 // Scalars of one half step, out[e][0][i] = A_i i!, out[e][1][i] = B_i i!
 // (i <= 3m): one thread per (source e, i).
+// use_series = 0: the unit-series source term (amplitude gradients).
 __global__ void source_scalars_kernel(const SourceDesc* __restrict__ srcs, uint32_t ns, uint32_t from,
-                                      int64_t host_steps, double* __restrict__ out) {
+                                      int64_t host_steps, uint32_t use_series, double* __restrict__ out) {
     const uint32_t e = blockIdx.x, i = threadIdx.x;
     if (e >= ns) return;
     const SourceDesc& S = srcs[e];
@@ -83,8 +84,9 @@ __global__ void source_scalars_kernel(const SourceDesc* __restrict__ srcs, uint3
         l2i *= S.lam * S.lam;
         ifact *= (double)l;
     }
-    out[(size_t)e * 20 + i] = S.pre * a * l2i * S.lam * ifact;
-    out[(size_t)e * 20 + 10 + i] = S.pre * b * l2i * ifact;
+    const double f = (use_series && S.series) ? S.series[2 * steps + from] : 1.0;
+    out[(size_t)e * 20 + i] = f * S.pre * a * l2i * S.lam * ifact;
+    out[(size_t)e * 20 + 10 + i] = f * S.pre * b * l2i * ifact;
 }
 
 // Scaled Taylor coefficients g1[a], a < 2M, of the 1D Gaussian factor about
@@ -147,68 +149,97 @@ __device__ __forceinline__ void axis_terms_rt(const double* g1, int j, double* D
 // One thread per (box cell, j3): the M^2 outputs (j1, j2) of that j3, both
 // fields, P_j = sum_e i!/(e1! e2! e3!) [A_i | B_i] prod_x D_x(j_x, e_x),
 // i = |e|. AB: this source's scalars (A_i i!, B_i i!).
-template <int M>
+// DOT = false: add the source term to the destination grid. DOT = true:
+// instead write this block's share of <grid[1 - from], source term> to
+// partial[blockIdx.x] (a fixed-order tree sum over the block).
+template <int M, bool DOT>
 __global__ __launch_bounds__(kThreads) void source_kernel(const SourceDesc* __restrict__ srcs,
                                                           const uint32_t* __restrict__ prefix, uint32_t ns,
-                                                          uint32_t from, const double* __restrict__ scal) {
+                                                          uint32_t from, const double* __restrict__ scal,
+                                                          double* __restrict__ partial) {
     const uint32_t gi = batch::find_entry(prefix, ns, blockIdx.x);
     const SourceDesc& S = srcs[gi];
     const uint32_t* box = S.box[from];
     const uint32_t n = S.n, nbx = box[3], nby = box[4], nbz = box[5];
     const uint64_t t = (uint64_t)(blockIdx.x - prefix[gi]) * kThreads + threadIdx.x;
-    if (t >= (uint64_t)nbx * nby * nbz * M) return;
-    const uint32_t cellk = (uint32_t)(t / M);  // box cells <= n^3 < 2^32
-    const int j3 = (int)(t % M);
-    const uint32_t ib = cellk % nbx, rest = cellk / nbx, jb = rest % nby, kb = rest / nby;
-    const uint32_t i = (box[0] + ib) % n, j = (box[1] + jb) % n, k = (box[2] + kb) % n;
-    // cell centre: lower corner + h/2 on the source grid (the dual grid sits
-    // h/2 further along every axis)
-    const double off_pos = from ? 0.5 : 0.0;
-    double g1[3][2 * M];
-    gauss_coeffs<M>(((double)i + 0.5 + off_pos) * S.h, S.x[0], S.sigma, S.h, g1[0]);
-    gauss_coeffs<M>(((double)j + 0.5 + off_pos) * S.h, S.x[1], S.sigma, S.h, g1[1]);
-    gauss_coeffs<M>(((double)k + 0.5 + off_pos) * S.h, S.x[2], S.sigma, S.h, g1[2]);
-    double D3[M];
-    axis_terms_rt<M>(g1[2], j3, D3);
-    const double* __restrict__ AB = scal + (size_t)gi * 20;
-    double A[3 * M - 2], Bv[3 * M - 2];
+    double dot = 0.0;
+    if (t < (uint64_t)nbx * nby * nbz * M) {
+        const uint32_t cellk = (uint32_t)(t / M);  // box cells <= n^3 < 2^32
+        const int j3 = (int)(t % M);
+        const uint32_t ib = cellk % nbx, rest = cellk / nbx, jb = rest % nby, kb = rest / nby;
+        const uint32_t i = (box[0] + ib) % n, j = (box[1] + jb) % n, k = (box[2] + kb) % n;
+        // cell centre: lower corner + h/2 on the source grid (the dual grid sits
+        // h/2 further along every axis)
+        const double off_pos = from ? 0.5 : 0.0;
+        double g1[3][2 * M];
+        gauss_coeffs<M>(((double)i + 0.5 + off_pos) * S.h, S.x[0], S.sigma, S.h, g1[0]);
+        gauss_coeffs<M>(((double)j + 0.5 + off_pos) * S.h, S.x[1], S.sigma, S.h, g1[1]);
+        gauss_coeffs<M>(((double)k + 0.5 + off_pos) * S.h, S.x[2], S.sigma, S.h, g1[2]);
+        double D3[M];
+        axis_terms_rt<M>(g1[2], j3, D3);
+        const double* __restrict__ AB = scal + (size_t)gi * 20;
+        double A[3 * M - 2], Bv[3 * M - 2];
 #pragma unroll
-    for (int r = 0; r < 3 * M - 2; ++r) {
-        A[r] = AB[r];
-        Bv[r] = AB[10 + r];
-    }
-    const double inv_fact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
-    // the dual cell with lower corner (i, j, k) writes primal node (i+1, j+1, k+1)
-    const uint32_t o = from ? 1u : 0u;
-    const size_t node = ((size_t)((k + o) % n) * n + (j + o) % n) * n + (i + o) % n;
-    double* __restrict__ dst = S.grid[1 - from];
-    constexpr int M3 = M * M * M;
+        for (int r = 0; r < 3 * M - 2; ++r) {
+            A[r] = AB[r];
+            Bv[r] = AB[10 + r];
+        }
+        const double inv_fact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
+        // the dual cell with lower corner (i, j, k) writes primal node (i+1, j+1, k+1)
+        const uint32_t o = from ? 1u : 0u;
+        const size_t node = ((size_t)((k + o) % n) * n + (j + o) % n) * n + (i + o) % n;
+        double* __restrict__ dst = S.grid[1 - from];
+        constexpr int M3 = M * M * M;
 #pragma unroll
-    for (int j2 = 0; j2 < M; ++j2) {
-        double D2[M];
-        axis_terms<M>(g1[1], j2, D2);
+        for (int j2 = 0; j2 < M; ++j2) {
+            double D2[M];
+            axis_terms<M>(g1[1], j2, D2);
 #pragma unroll
-        for (int j1 = 0; j1 < M; ++j1) {
-            double D1[M];
-            axis_terms<M>(g1[0], j1, D1);
-            double pu = 0.0, pv = 0.0;
-            // e_x <= (2M-1-j_x)/2: terms beyond degree 2M-1 are zero (for
-            // the runtime j3 the zero D3 entries do that)
+            for (int j1 = 0; j1 < M; ++j1) {
+                double D1[M];
+                axis_terms<M>(g1[0], j1, D1);
+                double pu = 0.0, pv = 0.0;
+                // e_x <= (2M-1-j_x)/2: terms beyond degree 2M-1 are zero (for
+                // the runtime j3 the zero D3 entries do that)
 #pragma unroll
-            for (int e3 = M - 1; e3 >= 0; --e3)
+                for (int e3 = M - 1; e3 >= 0; --e3)
 #pragma unroll
-                for (int e2 = (2 * M - 1 - j2) / 2; e2 >= 0; --e2)
+                    for (int e2 = (2 * M - 1 - j2) / 2; e2 >= 0; --e2)
 #pragma unroll
-                    for (int e1 = (2 * M - 1 - j1) / 2; e1 >= 0; --e1) {
-                        const double w = D1[e1] * D2[e2] * D3[e3] * (inv_fact[e1] * inv_fact[e2] * inv_fact[e3]);
-                        pu = fma(A[e1 + e2 + e3], w, pu);
-                        pv = fma(Bv[e1 + e2 + e3], w, pv);
-                    }
-            const int jj = (j3 * M + j2) * M + j1;
-            dst[(size_t)jj * S.pitch + node] += S.amp * pu;
-            dst[(size_t)(M3 + jj) * S.pitch + node] += S.amp * pv;
+                        for (int e1 = (2 * M - 1 - j1) / 2; e1 >= 0; --e1) {
+                            const double w = D1[e1] * D2[e2] * D3[e3] * (inv_fact[e1] * inv_fact[e2] * inv_fact[e3]);
+                            pu = fma(A[e1 + e2 + e3], w, pu);
+                            pv = fma(Bv[e1 + e2 + e3], w, pv);
+                        }
+                const int jj = (j3 * M + j2) * M + j1;
+                if constexpr (DOT) {
+                    dot = fma(dst[(size_t)jj * S.pitch + node], S.amp * pu, dot);
+                    dot = fma(dst[(size_t)(M3 + jj) * S.pitch + node], S.amp * pv, dot);
+                } else {
+                    dst[(size_t)jj * S.pitch + node] += S.amp * pu;
+                    dst[(size_t)(M3 + jj) * S.pitch + node] += S.amp * pv;
+                }
+            }
         }
     }
+    if constexpr (DOT) {
+        __shared__ double red[kThreads];
+        red[threadIdx.x] = dot;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    }
+}
+
+// grad = sum of the blocks' partial dot products, in block order.
+__global__ void sum_partials_kernel(const double* __restrict__ partial, uint32_t blocks, double* __restrict__ grad) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (uint32_t b = 0; b < blocks; ++b) s += partial[b];
+    *grad = s;
 }
 
 __global__ void advance_clock_kernel(SourceDesc* __restrict__ srcs, uint32_t ns) {
@@ -228,13 +259,34 @@ hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_
                          long long host_steps, double* scal, hipStream_t st) {
     if (blocks == 0 || ns == 0) return hipSuccess;
     hipLaunchKernelGGL(source_scalars_kernel, dim3(ns), dim3(16), 0, st, srcs, ns, (uint32_t)from,
-                       (int64_t)host_steps, scal);
+                       (int64_t)host_steps, 1u, scal);
+    const double* sc = scal;
+    double* none = nullptr;
     switch (m) {
-        case 1: hipLaunchKernelGGL(source_kernel<2>, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, (const double*)scal); break;
-        case 2: hipLaunchKernelGGL(source_kernel<3>, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, (const double*)scal); break;
-        case 3: hipLaunchKernelGGL(source_kernel<4>, dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, (const double*)scal); break;
+        case 1: hipLaunchKernelGGL((source_kernel<2, false>), dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, sc, none); break;
+        case 2: hipLaunchKernelGGL((source_kernel<3, false>), dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, sc, none); break;
+        case 3: hipLaunchKernelGGL((source_kernel<4, false>), dim3(blocks), dim3(kThreads), 0, st, srcs, prefix, ns, (uint32_t)from, sc, none); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_source_dot(const SourceDesc* src, const uint32_t* prefix, uint32_t blocks, int m, int from,
+                             long long host_steps, double* scal, double* partial, double* grad, hipStream_t st) {
+    if (blocks == 0) {
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, st, (const double*)partial, 0u, grad);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(source_scalars_kernel, dim3(1), dim3(16), 0, st, src, 1u, (uint32_t)from,
+                       (int64_t)host_steps, 0u, scal);
+    const double* sc = scal;
+    switch (m) {
+        case 1: hipLaunchKernelGGL((source_kernel<2, true>), dim3(blocks), dim3(kThreads), 0, st, src, prefix, 1u, (uint32_t)from, sc, partial); break;
+        case 2: hipLaunchKernelGGL((source_kernel<3, true>), dim3(blocks), dim3(kThreads), 0, st, src, prefix, 1u, (uint32_t)from, sc, partial); break;
+        case 3: hipLaunchKernelGGL((source_kernel<4, true>), dim3(blocks), dim3(kThreads), 0, st, src, prefix, 1u, (uint32_t)from, sc, partial); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, st, (const double*)partial, blocks, grad);
     return hipGetLastError();
 }
 
