@@ -52,7 +52,8 @@ struct hermite_ctx {
     long long series_len = 0;                 // amplitude series length (half steps), 0 = none
     uint32_t* d_rec = nullptr;                // receiver nodes (flat primal indices)
     uint32_t nrec = 0;
-    void* Kadj = nullptr;                     // canonical class operators (adjoint kernel)
+    void* Kadj = nullptr;                     // adjoint operator (canonical, or the m = 3 matrix-core layout)
+    double* E = nullptr;                      // m = 3 adjoint scratch: 8 vertices x 128 columns per cell
     double* d_partial = nullptr;              // source-gradient block partials
     uint32_t partial_cap = 0;                 // doubles in d_partial
     bool adjoint = false;                     // grids hold an adjoint state
@@ -97,6 +98,7 @@ void free_all(hermite_ctx* ctx) {
     if (ctx->d_source_scal) { (void)hipFree(ctx->d_source_scal); ctx->d_source_scal = nullptr; }
     if (ctx->d_rec) { (void)hipFree(ctx->d_rec); ctx->d_rec = nullptr; }
     if (ctx->Kadj) { (void)hipFree(ctx->Kadj); ctx->Kadj = nullptr; }
+    if (ctx->E) { (void)hipFree(ctx->E); ctx->E = nullptr; }
     if (ctx->d_partial) { (void)hipFree(ctx->d_partial); ctx->d_partial = nullptr; }
     if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
 }
@@ -478,6 +480,17 @@ int hermite_set_receivers(hermite_ctx* ctx, int n_rec, const int* ijk) {
 
 namespace {
 
+// One transposed half step: lam_src from lam_dst (off as the forward half step).
+hipError_t adjoint_half(hermite_ctx* ctx, const double* lam_dst, double* lam_src, int off) {
+    if (ctx->m == 3) {
+        const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
+        return hermite::launch_adjoint_mfma(lam_dst, lam_src, ctx->E, (const double*)ctx->Kadj, ctx->n, ctx->pitch,
+                                            off, grid, ctx->stream);
+    }
+    return hermite::launch_adjoint(ctx->m, lam_dst, lam_src, (const double*)ctx->Kadj, ctx->n, ctx->pitch, off,
+                                   ctx->stream);
+}
+
 int adjoint_supported(hermite_ctx* ctx) {
     if (ctx->nf != 2 || ctx->precision != HERMITE_PREC_FP64)
         return fail(ctx, HERMITE_EUNSUPPORTED, "the adjoint needs the wave equation in FP64");
@@ -496,7 +509,13 @@ int hermite_adjoint_init(hermite_ctx* ctx, const void* lam_u_dev, const void* la
     if ((rc = select_device(ctx)) != HERMITE_OK) return rc;
     if (!ctx->Kadj) {
         const std::vector<double> cpoly = hermite::evolution_poly(ctx->m, ctx->opt.evolution, ctx->q, ctx->substeps);
-        const std::vector<double> K = hermite::fused_class_operators(ctx->m, ctx->lam, cpoly);
+        std::vector<double> K = hermite::fused_class_operators(ctx->m, ctx->lam, cpoly);
+        if (ctx->m == 3) {
+            std::vector<double> KT(hermite::adjoint_mfma_operator_doubles());
+            hermite::adjoint_mfma_build_operator(K.data(), KT.data());
+            K.swap(KT);
+            HCHECK(ctx, hipMalloc(&ctx->E, (size_t)1024 * ctx->pitch * sizeof(double)), "hipMalloc(adjoint scratch)");
+        }
         HCHECK(ctx, hipMalloc(&ctx->Kadj, K.size() * sizeof(double)), "hipMalloc(adjoint operator)");
         HCHECK(ctx, hipMemcpy(ctx->Kadj, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice),
                "upload adjoint operator");
@@ -552,17 +571,13 @@ int hermite_adjoint_step(hermite_ctx* ctx, int n_full_steps, const void* res_dev
                                                    1, k, ctx->d_source_scal, ctx->d_partial,
                                                    (double*)grad_amps_dev + 2 * s + 1, ctx->stream),
                    "source gradient launch");
-        HCHECK(ctx, hermite::launch_adjoint(ctx->m, lam_p, lam_d, (const double*)ctx->Kadj, ctx->n, ctx->pitch, 1,
-                                            ctx->stream),
-               "adjoint half-step launch");
+        HCHECK(ctx, adjoint_half(ctx, lam_p, lam_d, 1), "adjoint half-step launch");
         if (grad_amps_dev)
             HCHECK(ctx, hermite::launch_source_dot(ctx->d_source, ctx->d_source_prefix, ctx->source_blocks[0], ctx->m, 0,
                                                    k, ctx->d_source_scal, ctx->d_partial,
                                                    (double*)grad_amps_dev + 2 * s, ctx->stream),
                    "source gradient launch");
-        HCHECK(ctx, hermite::launch_adjoint(ctx->m, lam_d, lam_p, (const double*)ctx->Kadj, ctx->n, ctx->pitch, 0,
-                                            ctx->stream),
-               "adjoint half-step launch");
+        HCHECK(ctx, adjoint_half(ctx, lam_d, lam_p, 0), "adjoint half-step launch");
     }
     ctx->adj_steps = t0;
     return HERMITE_OK;

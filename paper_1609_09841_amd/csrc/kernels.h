@@ -91,6 +91,15 @@ hipError_t launch_source_dot(const SourceDesc* src, const uint32_t* prefix, uint
 // class operators ([8][rows_max][2 M^3], fused_class_operators), device.
 hipError_t launch_adjoint(int m, const double* lam_dst, double* lam_src, const double* K, int n, size_t pitch, int off,
                           hipStream_t st);
+// m = 3 on the matrix cores: KT = adjoint_mfma_build_operator(K)
+// (adjoint_mfma_operator_doubles() doubles); E: scratch of 1024 columns of
+// `pitch` doubles (8 vertices x 128 columns per cell); grid as for
+// launch_fused_mfma. Two launches: per-cell vertex contributions, then the
+// per-node sum.
+hipError_t launch_adjoint_mfma(const double* lam_dst, double* lam_src, double* E, const double* KT, int n,
+                               size_t pitch, int off, int grid, hipStream_t st);
+size_t adjoint_mfma_operator_doubles();
+void adjoint_mfma_build_operator(const double* K, double* KT);
 // Receivers: traces[r] = grid[nodes[r]] (u, d = 0 of the primal grid);
 // inject: lam[nodes[r]] += res[r] in receiver order.
 hipError_t launch_record(const double* grid, const uint32_t* nodes, uint32_t nr, double* traces, hipStream_t st);
