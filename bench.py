@@ -356,9 +356,32 @@ def cpu_baseline(m: int, n_s: int) -> dict:
     O.run(n_s, m, 0.5, 1.0, u0, ut0, 1)
     sec = time.perf_counter() - t0
     dofs = 2 * (m + 1) ** 3 * n_s ** 3 * 2 * 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    # one thread, in a child process (the OpenMP team size is fixed once the
+    # oracle library is loaded): a 32^3 sample of the same recipe
+    single = None
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\nfrom paper_1609_09841_amd import inputs as I\n"
+            "u0, ut0 = I.fourier_initial(32, %d)\nt0 = time.perf_counter()\n"
+            "O.run(32, %d, 0.5, 1.0, u0.numpy(), ut0.numpy(), 1)\nprint(time.perf_counter() - t0)\n") % (ROOT, m, m)
+    try:
+        import subprocess
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                           env=dict(os.environ, OMP_NUM_THREADS="1"))
+        s1 = float(r.stdout.strip().splitlines()[-1])
+        single = {"value": 2 * (m + 1) ** 3 * 32 ** 3 * 2 / s1, "cores": 1,
+                  "sample": f"32^3 cells, m={m}, 1 full step, {s1:.2f} s on 1 thread"}
+    except Exception as exc:  # reported, not fatal
+        single = {"error": str(exc)}
     return {"value": dofs / sec, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_s}^3 cells, m={m}, 1 full step (2 half steps) of the same Fourier-mode "
-                      f"workload, {sec:.2f} s on {cores} threads"}
+                      f"workload, {sec:.2f} s on {cores} threads",
+            "cpu_model": model, "single_thread": single}
 
 
 def main():

@@ -226,6 +226,11 @@ int hermite_adjoint_step(hermite_ctx *ctx, int n_full_steps, const void *res_dev
  * the sweep's current time, to device arrays (either may be NULL). */
 int hermite_adjoint_gather(hermite_ctx *ctx, void *gu_dev, void *gut_dev);
 
+/* Failure detection: *all_finite = 1 if every DOF of the state (or of the
+ * adjoint state during an adjoint sweep) is finite, else 0 (NaN or Inf, e.g.
+ * after running beyond the stable cfl range). Waits for the stream. */
+int hermite_state_finite(hermite_ctx *ctx, int *all_finite);
+
 /* Waits for all work enqueued on the context's stream. */
 int hermite_sync(hermite_ctx *ctx);
 

@@ -45,7 +45,7 @@ EXPORTS = (
     "hermite_batch_default_options", "hermite_batch_create", "hermite_batch_set_initial", "hermite_batch_step",
     "hermite_batch_gather", "hermite_batch_sync", "hermite_batch_tuning", "hermite_batch_destroy",
     "hermite_batch_last_error", "hermite_set_receivers", "hermite_set_source_series", "hermite_step_record",
-    "hermite_adjoint_init", "hermite_adjoint_step", "hermite_adjoint_gather",
+    "hermite_adjoint_init", "hermite_adjoint_step", "hermite_adjoint_gather", "hermite_state_finite",
 )
 
 
@@ -138,6 +138,8 @@ def load(path: str = LIB_PATH):
     lib.hermite_set_source.restype = ip
     lib.hermite_last_error.argtypes = [vp]
     lib.hermite_last_error.restype = ctypes.c_char_p
+    lib.hermite_state_finite.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.hermite_state_finite.restype = ip
     lib.hermite_set_receivers.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.hermite_set_receivers.restype = ip
     lib.hermite_set_source_series.argtypes = [vp, vp, ctypes.c_longlong]
@@ -319,6 +321,12 @@ class Solver:
 
     def sync(self):
         _check(self._lib.hermite_sync(self._ctx), self._ctx)
+
+    def finite(self) -> bool:
+        """True if every DOF of the (adjoint) state is finite."""
+        f = ctypes.c_int()
+        _check(self._lib.hermite_state_finite(self._ctx, ctypes.byref(f)), self._ctx)
+        return bool(f.value)
 
     def gather(self):
         """(u, ut, t) as numpy arrays shaped (M, M, M, n, n, n); ut is None

@@ -97,6 +97,7 @@ int bfail(hermite_batch* b, int code, const char* fmt, ...) {
 }
 
 int bhip(hermite_batch* b, hipError_t e, const char* what) {
+    (void)hipGetLastError();  // clear the thread's last error (see capi.cpp)
     return bfail(b, (e == hipErrorOutOfMemory) ? HERMITE_ENOMEM : HERMITE_EDEVICE, "%s: %s (%d)", what,
                  hipGetErrorString(e), (int)e);
 }
@@ -235,6 +236,7 @@ int upload(hermite_batch* b, T** dptr, const std::vector<T>& v, const char* what
 int check_shot(hermite_batch* b, int shot) {
     if (!b) return bfail(nullptr, HERMITE_EINVAL, "batch is NULL");
     if (shot < 0 || shot >= b->n_shots) return bfail(b, HERMITE_EINVAL, "shot=%d outside [0, %d)", shot, b->n_shots);
+    (void)hipGetLastError();
     BCHECK(b, hipSetDevice(b->device), "hipSetDevice");
     return HERMITE_OK;
 }
@@ -304,6 +306,7 @@ int hermite_batch_create(int n_shots, const hermite_shot* shots, double cfl, dou
         delete b;
         return code;
     };
+    (void)hipGetLastError();  // start from a clean last-error state
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) return bail(bhip(b, e, "hipGetDevice"));
     if ((e = hipSetDevice(b->device)) != hipSuccess) return bail(bhip(b, e, "hipSetDevice"));
@@ -460,6 +463,7 @@ int hermite_batch_set_initial(hermite_batch* b, int shot, const double* u, const
 int hermite_batch_step(hermite_batch* b, int n_full_steps) {
     if (!b) return bfail(nullptr, HERMITE_EINVAL, "batch is NULL");
     if (n_full_steps < 0) return bfail(b, HERMITE_EINVAL, "n_full_steps=%d < 0", n_full_steps);
+    (void)hipGetLastError();
     BCHECK(b, hipSetDevice(b->device), "hipSetDevice");
     if (n_full_steps == 0) return HERMITE_OK;
     if (b->opt.graph) {

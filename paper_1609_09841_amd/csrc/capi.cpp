@@ -77,6 +77,9 @@ int fail(hermite_ctx* ctx, int code, const char* fmt, ...) {
 }
 
 int hip_fail(hermite_ctx* ctx, hipError_t e, const char* what) {
+    // the runtime keeps the error as the thread's last error: clear it, so
+    // that a later launch check does not report it again
+    (void)hipGetLastError();
     return fail(ctx, (e == hipErrorOutOfMemory) ? HERMITE_ENOMEM : HERMITE_EDEVICE, "%s: %s (%d)", what,
                 hipGetErrorString(e), (int)e);
 }
@@ -104,6 +107,9 @@ void free_all(hermite_ctx* ctx) {
 }
 
 int select_device(hermite_ctx* ctx) {
+    // a failed runtime call elsewhere in this thread leaves its error as the
+    // last error; start from a clean state so launch checks see our own
+    (void)hipGetLastError();
     HCHECK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     return HERMITE_OK;
 }
@@ -231,6 +237,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         return code;
     };
     int rc = HERMITE_OK;
+    (void)hipGetLastError();  // start from a clean last-error state
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipGetDevice"));
     if ((rc = select_device(ctx)) != HERMITE_OK) return bail(rc);
@@ -597,6 +604,26 @@ int hermite_adjoint_gather(hermite_ctx* ctx, void* gu_dev, void* gut_dev) {
         HCHECK(ctx, hermite::launch_scale((double*)gut_dev, ctx->ncell, gv, ctx->pitch, ctx->h / ctx->c, ctx->ncell,
                                           ctx->M3, ctx->stream),
                "scale gut");
+    return HERMITE_OK;
+}
+
+int hermite_state_finite(hermite_ctx* ctx, int* all_finite) {
+    if (!ctx) return fail(nullptr, HERMITE_EINVAL, "ctx is NULL");
+    if (!all_finite) return fail(ctx, HERMITE_EINVAL, "all_finite is NULL");
+    if (!ctx->has_state && !ctx->adjoint) return fail(ctx, HERMITE_ESTATE, "hermite_state_finite before a state");
+    int rc = select_device(ctx);
+    if (rc) return rc;
+    int* flag = nullptr;
+    HCHECK(ctx, hipMalloc(&flag, sizeof(int)), "hipMalloc(flag)");
+    int host = 0;
+    hipError_t e = hipMemcpyAsync(flag, &host, sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hermite::launch_nonfinite(ctx->grid[0], ctx->pitch, ctx->ncell, ctx->nf * ctx->M3, flag, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(flag);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finite check");
+    *all_finite = host ? 0 : 1;
     return HERMITE_OK;
 }
 

@@ -145,6 +145,9 @@ hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, 
 hipError_t launch_evolve(int m, const double* R, double* dst, int n, size_t pitch, int off, int evolution,
                          int q, int S, double lam, hipStream_t st);
 
+// *flag |= 1 if any entry g[r * pitch + c], r < rows, c < cols, is NaN or Inf.
+hipError_t launch_nonfinite(const double* g, size_t pitch, size_t cols, int rows, int* flag, hipStream_t st);
+
 // dst[r * dpitch + c] = s * src[r * spitch + c], r < rows, c < cols (dst may equal src).
 hipError_t launch_scale(double* dst, size_t dpitch, const double* src, size_t spitch, double s, size_t cols,
                         int rows, hipStream_t st);

@@ -20,6 +20,7 @@
 // rounding of the sums below that of a plain ascending loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -267,7 +268,22 @@ __global__ void scale_kernel(double* __restrict__ dst, size_t dpitch, const doub
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cols; i += stride) b[i] = s * a[i];
 }
 
+// flag = 1 if any of rows x cols entries (row r at r * pitch) is NaN or Inf.
+__global__ void nonfinite_kernel(const double* __restrict__ g, size_t pitch, size_t cols, int* __restrict__ flag) {
+    const double* __restrict__ a = g + (size_t)blockIdx.y * pitch;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cols; i += stride) bad |= !isfinite(a[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 }  // namespace
+
+hipError_t launch_nonfinite(const double* g, size_t pitch, size_t cols, int rows, int* flag, hipStream_t st) {
+    const uint32_t bx = (uint32_t)std::min<size_t>((cols + 255) / 256, 1024);
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(bx, rows), dim3(256), 0, st, g, pitch, cols, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch, hipStream_t st) {
     const uint32_t ncell = (uint32_t)n * n * n;
