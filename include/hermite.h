@@ -65,9 +65,10 @@ extern "C" {
 /* Equation (Sec. 2). WAVE: u_tt = c^2 Lap u as the first-order system
  * (u, u_t), two fields per node. ADVECTION: u_t = c (u_x1 + u_x2 + u_x3),
  * the paper's Eq. 1 (c = 1), one field per node: set_initial and gather then
- * ignore ut (it may be NULL). Advection needs FP64, Taylor evolution with
- * q = 0 or q >= 3(2m+1) (the series is then exact, Sec. 3.2) and the fused
- * kernel, HERMITE_EUNSUPPORTED otherwise; it has no point source. */
+ * ignore ut (it may be NULL). Advection needs FP64 and Taylor evolution with
+ * q = 0 or q >= 3(2m+1) (the series is then exact, Sec. 3.2),
+ * HERMITE_EUNSUPPORTED otherwise; both kernel organisations (fused and two
+ * kernels); it has no point source. */
 #define HERMITE_EQ_WAVE 0
 #define HERMITE_EQ_ADVECTION 1
 

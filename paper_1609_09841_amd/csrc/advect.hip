@@ -96,7 +96,81 @@ hipError_t launch_m(const double* src, double* dst, const double* K1, int n, siz
     return hipGetLastError();
 }
 
+// Two-kernel variant, evolution half: R holds each cell's monomial
+// coefficients R[k3][k2][k1] (P^3 columns); the evolved polynomial
+// p(xi + lam (1,1,1)) keeps y[j] = sum_k E1[j3][k3] E1[j2][k2] E1[j1][k1] R[k],
+// j <= m, sum-factorised like the fused kernel (one lane per cell, streaming
+// over (k3, k2), E1 as scalar operands): M P^3 + M^2 P^2 + M^3 P FMAs.
+template <int M>
+struct EvolveOp {
+    double e[M * 2 * M];  // E1[j][k], row-major, k < P
+};
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void advect_evolve_kernel(const double* __restrict__ R,
+                                                                 double* __restrict__ dst, EvolveOp<M> E,
+                                                                 uint32_t n, size_t pitch, uint32_t off) {
+    constexpr int P = 2 * M, M3 = M * M * M;
+    const uint32_t cell = blockIdx.x * kThreads + threadIdx.x;
+    if (cell >= n * n * n) return;
+    const Cell16 c = cell_nodes(cell, n, off);
+    double y[M3];
+#pragma unroll
+    for (int t = 0; t < M3; ++t) y[t] = 0.0;
+    // high orders (small terms) first
+#pragma unroll
+    for (int k3 = P - 1; k3 >= 0; --k3) {
+        double Y[M * M];
+#pragma unroll
+        for (int t = 0; t < M * M; ++t) Y[t] = 0.0;
+#pragma unroll
+        for (int k2 = P - 1; k2 >= 0; --k2) {
+            double x[P];
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) x[k1] = R[(size_t)((k3 * P + k2) * P + k1) * pitch + cell];
+#pragma unroll
+            for (int j1 = 0; j1 < M; ++j1) {
+                double z = 0.0;
+#pragma unroll
+                for (int k1 = P - 1; k1 >= j1; --k1) z = __builtin_fma(E.e[j1 * P + k1], x[k1], z);
+#pragma unroll
+                for (int j2 = 0; j2 < M; ++j2)
+                    if (k2 >= j2) Y[j2 * M + j1] = __builtin_fma(E.e[j2 * P + k2], z, Y[j2 * M + j1]);
+            }
+        }
+#pragma unroll
+        for (int j3 = 0; j3 < M; ++j3)
+            if (k3 >= j3)
+#pragma unroll
+                for (int t = 0; t < M * M; ++t)
+                    y[j3 * M * M + t] = __builtin_fma(E.e[j3 * P + k3], Y[t], y[j3 * M * M + t]);
+    }
+#pragma unroll
+    for (int t = 0; t < M3; ++t) dst[(size_t)t * pitch + c.out] = y[t];
+}
+
+template <int M>
+hipError_t launch_evolve_m(const double* R, double* dst, const double* E1, int n, size_t pitch, int off,
+                           hipStream_t st) {
+    EvolveOp<M> op;
+    for (int i = 0; i < M * 2 * M; ++i) op.e[i] = E1[i];
+    const uint32_t ncell = (uint32_t)n * n * n;
+    hipLaunchKernelGGL(advect_evolve_kernel<M>, dim3((ncell + kThreads - 1) / kThreads), dim3(kThreads), 0, st, R,
+                       dst, op, (uint32_t)n, pitch, (uint32_t)off);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_advect_evolve(int m, const double* R, double* dst, const double* E1, int n, size_t pitch, int off,
+                                hipStream_t st) {
+    switch (m) {
+        case 1: return launch_evolve_m<2>(R, dst, E1, n, pitch, off, st);
+        case 2: return launch_evolve_m<3>(R, dst, E1, n, pitch, off, st);
+        case 3: return launch_evolve_m<4>(R, dst, E1, n, pitch, off, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_advect(int m, const double* src, double* dst, const double* K1, int n, size_t pitch, int off,
                          hipStream_t st) {

@@ -34,6 +34,7 @@ struct hermite_ctx {
     int precision = 0;       // HERMITE_PREC_*: contraction arithmetic
     int nf = 2;              // fields per node: 2 (wave: u, u_t) or 1 (advection)
     std::vector<double> K1;  // advection: per-axis operator (M x 2M)
+    std::vector<double> E1;  // advection, two kernels: per-axis translation (M x P)
     double* grid[2] = {nullptr, nullptr};  // primal, dual: 2 M^3 columns of `pitch` doubles each
     double* R = nullptr;                   // two-kernel scratch: 2 P^3 columns of `pitch` doubles
     size_t ncell = 0;                      // n^3 nodes per column
@@ -121,9 +122,14 @@ int half_step(hermite_ctx* ctx, int from) {
     if (ctx->opt.poison)
         HCHECK(ctx, hipMemsetAsync(dst, 0xFF, ctx->grid_doubles * sizeof(double), ctx->stream), "poison");
     hipError_t e;
-    if (ctx->nf == 1) {
+    if (ctx->nf == 1 && ctx->opt.fused) {
         e = hermite::launch_advect(ctx->m, src, dst, ctx->K1.data(), ctx->n, ctx->pitch, off, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "advection half-step launch");
+    } else if (ctx->nf == 1) {
+        e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->pitch, 1, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "interpolation launch");
+        e = hermite::launch_advect_evolve(ctx->m, ctx->R, dst, ctx->E1.data(), ctx->n, ctx->pitch, off, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "advection evolution launch");
     } else if (ctx->opt.fused) {
         const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
         if (ctx->precision != HERMITE_PREC_FP64) {
@@ -139,7 +145,7 @@ int half_step(hermite_ctx* ctx, int from) {
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "fused half-step launch");
     } else {
-        e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->pitch, ctx->stream);
+        e = hermite::launch_interp(ctx->m, src, ctx->R, ctx->Hp, ctx->n, ctx->pitch, 2, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "interpolation launch");
         e = hermite::launch_evolve(ctx->m, ctx->R, dst, ctx->n, ctx->pitch, off, ctx->opt.evolution, ctx->q,
                                    ctx->substeps, ctx->lam, ctx->stream);
@@ -192,10 +198,10 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     if (o.equation != HERMITE_EQ_WAVE && o.equation != HERMITE_EQ_ADVECTION)
         return fail(nullptr, HERMITE_EINVAL, "equation=%d", o.equation);
     if (o.equation == HERMITE_EQ_ADVECTION) {
-        if (o.precision != HERMITE_PREC_FP64 || o.evolution != HERMITE_EVOLVE_TAYLOR || !o.fused)
+        if (o.precision != HERMITE_PREC_FP64 || o.evolution != HERMITE_EVOLVE_TAYLOR)
             return fail(nullptr, HERMITE_EUNSUPPORTED,
-                        "advection needs FP64, Taylor evolution and the fused kernel (precision=%d, evolution=%d, "
-                        "fused=%d)", o.precision, o.evolution, o.fused);
+                        "advection needs FP64 and Taylor evolution (precision=%d, evolution=%d)", o.precision,
+                        o.evolution);
         if (o.q != 0 && o.q < 3 * (2 * m + 1))
             return fail(nullptr, HERMITE_EUNSUPPORTED, "advection needs q = 0 or q >= 3(2m+1) = %d (q=%d)",
                         3 * (2 * m + 1), o.q);
@@ -209,7 +215,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     const size_t nn = (size_t)n_cells * n_cells * n_cells;
     const size_t pitch = hermite::column_pitch(nn);
     const size_t grid_doubles = (size_t)nf * M * M * M * pitch;
-    const size_t r_doubles = o.fused ? 0 : (size_t)2 * P * P * P * pitch;
+    const size_t r_doubles = o.fused ? 0 : (size_t)nf * P * P * P * pitch;
 
     hermite_ctx* ctx = new (std::nothrow) hermite_ctx();
     if (!ctx) return fail(nullptr, HERMITE_ENOMEM, "host allocation failed");
@@ -267,6 +273,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     std::vector<unsigned char> Kdev;
     if (nf == 1) {
         ctx->K1 = hermite::advection_axis_operator(m, ctx->lam);
+        ctx->E1 = hermite::advection_translation(m, ctx->lam);
     } else if (o.precision != HERMITE_PREC_FP64) {
         Kdev.resize(hermite::mixed_operator_bytes(o.precision));
         hermite::mixed_build_operators(o.precision, K.data(), Kdev.data());

@@ -165,6 +165,15 @@ std::vector<double> fused_class_operators(int m, double lam, const std::vector<d
     return K;
 }
 
+std::vector<double> advection_translation(int m, double lam) {
+    const int M = m + 1, P = 2 * m + 2;
+    std::vector<double> E((size_t)M * P, 0.0);
+    for (int j = 0; j < M; ++j)
+        for (int k = j; k < P; ++k)
+            E[(size_t)j * P + k] = (double)(binom(k, j) * std::pow((long double)lam, (long double)(k - j)));
+    return E;
+}
+
 std::vector<double> advection_axis_operator(int m, double lam) {
     const int M = m + 1, P = 2 * m + 2;
     const std::vector<double> H = hermite_matrix(m);

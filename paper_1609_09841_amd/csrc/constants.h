@@ -41,6 +41,9 @@ std::vector<double> fused_class_operators(int m, double lam, const std::vector<d
 // so interpolation, evolution and truncation compose per axis into
 // K1 = T E H, M x P row-major, K1[j][a] = sum_k C(k, j) lam^(k-j) H[k][a].
 std::vector<double> advection_axis_operator(int m, double lam);
+// The translation part alone, E[j][k] = C(k, j) lam^(k-j), M x P row-major
+// (rows j <= m): the evolution half of the two-kernel advection step.
+std::vector<double> advection_translation(int m, double lam);
 
 int rows_max(int m);
 int nout(int M, int p);

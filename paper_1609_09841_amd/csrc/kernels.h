@@ -134,10 +134,18 @@ hipError_t launch_advect(int m, const double* src, double* dst, const double* K1
                          hipStream_t st);
 
 // Interpolation half of the two-kernel variant: writes the monomial
-// coefficients R[2][P^3][n^3] (P = 2m+2) of every cell of src. Hp: parity
-// blocks of H, [2][M][M].
-hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch,
+// coefficients R[nf][P^3][n^3] (P = 2m+2) of every cell of src (nf fields:
+// 2 for the wave system, 1 for advection). Hp: parity blocks of H, [2][M][M].
+hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch, int nf,
                          hipStream_t st);
+
+// Advection evolution half of the two-kernel variant: reads R[P^3][n^3],
+// translates each cell polynomial by lam (1,1,1) (the exact Taylor series,
+// q >= 3(2m+1)) and writes the coefficients with every index <= m to node
+// cell + off of dst. E1: M x P row-major, E1[j][k] = C(k, j) lam^(k-j) (host
+// memory, passed by value).
+hipError_t launch_advect_evolve(int m, const double* R, double* dst, const double* E1, int n, size_t pitch, int off,
+                                hipStream_t st);
 
 // Evolution half: reads R, runs the Taylor stage loop (evolution 0, q stages)
 // or 4-stage Runge-Kutta (evolution 1, S substeps) with lam = c*tau/h, and

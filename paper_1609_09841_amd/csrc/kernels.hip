@@ -74,13 +74,15 @@ __device__ __forceinline__ double parity_sign(int p, int d) { return ((p + d) & 
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(256) void interp_kernel(const double* __restrict__ src, double* __restrict__ R,
-                                                     const double* __restrict__ Hp, uint32_t n, size_t pitch) {
+                                                     const double* __restrict__ Hp, uint32_t n, size_t pitch,
+                                                     uint32_t nf) {
     constexpr int M3 = M * M * M, P = 2 * M, P3 = P * P * P;
     const uint32_t ncell = n * n * n;
-    const uint32_t cell = (blockIdx.x >> 4) * 256u + threadIdx.x;
+    // blocks: (cell group, class, field) with field (of nf) fastest
+    const uint32_t cell = (blockIdx.x / (8 * nf)) * 256u + threadIdx.x;
     if (cell >= ncell) return;
     const CellIdx c = cell_index(cell, n, 0);
-    const int f = blockIdx.x & 1, pc = (blockIdx.x >> 1) & 7;
+    const int f = (int)(blockIdx.x % nf), pc = (int)((blockIdx.x / nf) & 7);
     const int p1 = pc & 1, p2 = (pc >> 1) & 1, p3 = pc >> 2;
     const double* __restrict__ H1 = Hp + p1 * M * M;
     const double* __restrict__ H2 = Hp + p2 * M * M;
@@ -285,14 +287,16 @@ hipError_t launch_nonfinite(const double* g, size_t pitch, size_t cols, int rows
     return hipGetLastError();
 }
 
-hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch, hipStream_t st) {
+hipError_t launch_interp(int m, const double* src, double* R, const double* Hp, int n, size_t pitch, int nf,
+                         hipStream_t st) {
+    if (nf != 1 && nf != 2) return hipErrorInvalidValue;
     const uint32_t ncell = (uint32_t)n * n * n;
-    const dim3 grid(16 * ((ncell + 255) / 256)), block(256);
-    const uint32_t un = (uint32_t)n;
+    const dim3 grid(8 * nf * ((ncell + 255) / 256)), block(256);
+    const uint32_t un = (uint32_t)n, unf = (uint32_t)nf;
     switch (m) {
-        case 1: hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, st, src, R, Hp, un, pitch); break;
-        case 2: hipLaunchKernelGGL(interp_kernel<3>, grid, block, 0, st, src, R, Hp, un, pitch); break;
-        case 3: hipLaunchKernelGGL(interp_kernel<4>, grid, block, 0, st, src, R, Hp, un, pitch); break;
+        case 1: hipLaunchKernelGGL(interp_kernel<2>, grid, block, 0, st, src, R, Hp, un, pitch, unf); break;
+        case 2: hipLaunchKernelGGL(interp_kernel<3>, grid, block, 0, st, src, R, Hp, un, pitch, unf); break;
+        case 3: hipLaunchKernelGGL(interp_kernel<4>, grid, block, 0, st, src, R, Hp, un, pitch, unf); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -186,7 +186,6 @@ def test_valid_batch_create_without_device_reports_device_error():
     ("equation", 2, B.HERMITE_EINVAL),
     ("precision", B.HERMITE_PREC_FP32, B.HERMITE_EUNSUPPORTED),
     ("evolution", B.HERMITE_EVOLVE_RK4, B.HERMITE_EUNSUPPORTED),
-    ("fused", 0, B.HERMITE_EUNSUPPORTED),
     ("q", 20, B.HERMITE_EUNSUPPORTED),   # below 3(2m+1) = 21 at m = 3
 ])
 def test_advection_options_validated(field, value, code):

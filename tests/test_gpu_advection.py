@@ -51,12 +51,24 @@ def _check(n, m, u0, steps, cfl=0.5, c=1.0, q=None, **kw):
     return e
 
 
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "two"])
 @pytest.mark.parametrize("m", [1, 2, 3])
 @pytest.mark.parametrize("n", [2, 3, 5, 8, 13])
-def test_random_data_small_grids(n, m):
+def test_random_data_small_grids(n, m, fused):
     M = m + 1
     u0 = np.random.default_rng(100 * n + m).standard_normal((M, M, M, n, n, n))
-    _check(n, m, u0, 2)
+    _check(n, m, u0, 2, fused=fused)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_two_kernel_organisation_matches_fused(m):
+    """Interpolation to the coefficients in memory, then the translation
+    kernel, against the fused kernel (independent code paths)."""
+    n = 11
+    u0, _ = I.fourier_initial(n, m, nmodes=3, kmax=2)
+    a, _ = gpu_advect(n, m, u0.numpy(), 5, fused=True)
+    b, _ = gpu_advect(n, m, u0.numpy(), 5, fused=False)
+    assert rel(b, a) <= (1e-13 if m < 3 else 1e-11)
 
 
 @pytest.mark.parametrize("m", [1, 2, 3])
@@ -134,8 +146,7 @@ def test_full_size_sampled_150_cube_m3():
 def test_advection_option_errors():
     o = B.hermite_default_options()
     o.equation = B.HERMITE_EQ_ADVECTION
-    for field, value in (("precision", B.HERMITE_PREC_FP32), ("evolution", B.HERMITE_EVOLVE_RK4), ("fused", 0),
-                         ("q", 6)):
+    for field, value in (("precision", B.HERMITE_PREC_FP32), ("evolution", B.HERMITE_EVOLVE_RK4), ("q", 6)):
         oo = B.hermite_options.from_buffer_copy(o)
         setattr(oo, field, value)
         rc, h = B.hermite_create(8, 2, 0.5, 1.0, oo)
