@@ -221,3 +221,22 @@ def test_full_size_shots_equal_single_runs_bitwise():
     for sh, (u0, ut0), (gu, gv, _) in zip(shots, data, res):
         su, sv, _ = _single(sh, u0.numpy(), ut0.numpy(), steps)
         assert np.array_equal(gu, su) and np.array_equal(gv, sv), (sh["n"], sh["m"])
+
+
+def test_graph_replays_interleaved_with_eager_work():
+    """Each replay of the captured step, with eager work of the library
+    (gathers: copies and scaling kernels) and synchronisations between
+    replays, equals the same steps launched directly."""
+    shots = _shots(13, 5, (7, 10, 16), (1, 2, 3), True)
+    data = [_initial(sh, 200 + i) for i, sh in enumerate(shots)]
+    with B.Batch(shots, graph=True) as g, B.Batch(shots, graph=False) as d:
+        for i, (u0, ut0) in enumerate(data):
+            g.set_initial(i, u0, ut0)
+            d.set_initial(i, u0, ut0)
+        for step in range(4):
+            g.step(1)
+            d.step(1)
+            for i in range(len(shots)):
+                a, b = g.gather(i), d.gather(i)
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (step, i)
+            g.sync()
