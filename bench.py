@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF-updates/s at m=3, plain FP64 vs mixed-precision at rel L2 <= 1e-6"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+MEASURED_FP64_MFMA_TFLOPS = 42.8  # v_mfma_f64_16x16x4f64 throughput measured on gfx950
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64, vector and matrix alike
 
 # Useful FP64 flops per cell per half step of the fused formulation: the
@@ -435,6 +436,10 @@ def main():
             roofline = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                         "kernel": "fused_mfma_kernel (FP64 MFMA 16x16x4)",
+                        # context: the FP64 MFMA rate measured on this chip by the committed
+                        # microbenchmark (profiles/mfma_throughput_gfx950.md)
+                        "measured_mfma_fp64_TFLOPs": MEASURED_FP64_MFMA_TFLOPS,
+                        "frac_of_measured_mfma": achieved / MEASURED_FP64_MFMA_TFLOPS,
                         "hbm_GBps_algorithmic": gbs, "hbm_frac_algorithmic": gbs / HBM_PEAK_GBS, **common}
         else:
             # m = 1, 2: 3.5 and 6.2 flop/B, below the ridge: HBM-bound
