@@ -109,15 +109,18 @@ struct ColTable {
 };
 __constant__ ColTable kColTable = ColTable();
 
-// One batch: 16 neighbouring cells of one x-row (cells x0 .. x0+15 of row
-// (y, z); lanes past the end of the row compute a copy of the last cell and
-// store nothing).
+// One batch: the 16 neighbouring cells of row (y, z) whose new nodes are
+// x0 .. x0+15 (lower corners x0 - off .., periodic); lanes past the end of
+// the row compute a copy of the last cell and store nothing.
 __device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t plane,
                                           uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
                                           int cl, int q, uint32_t* packed, const double* sK) {
     const uint32_t x = x0 + cl;
     const bool valid = x < n;
-    const Cell16 c = cell_nodes((z * n + y) * n + (valid ? x : n - 1), n, off);
+    // lane cl produces new node x0 + cl of row (y + off, z + off): the cell's
+    // lower corner is x - off, so that the stores of a batch fill whole
+    // 128-byte lines also in the dual -> primal half step
+    const Cell16 c = cell_nodes((z * n + y) * n + (valid ? (x + n - off) % n : n - 1), n, off);
     // Opaque per batch: without this the 32 per-lane column base addresses
     // are hoisted out of the batch loop and pin 64 registers.
 #pragma unroll
