@@ -361,10 +361,19 @@ def cpu_baseline(m: int, n_s: int) -> dict:
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     u0, ut0 = I.fourier_initial(n_s, m)
     u0, ut0 = u0.numpy(), ut0.numpy()
-    t0 = time.perf_counter()
+    c0, t0 = time.process_time(), time.perf_counter()
     O.run(n_s, m, 0.5, 1.0, u0, ut0, 1)
     sec = time.perf_counter() - t0
+    cpu = time.process_time() - c0   # summed over the process's threads
     dofs = 2 * (m + 1) ** 3 * n_s ** 3 * 2 * 1
+    # a CPU quota of the container caps the cores the threads really get
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, period = fh.read().split()
+            quota = None if q == "max" else float(q) / float(period)
+    except (OSError, ValueError):
+        pass
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -390,6 +399,7 @@ def cpu_baseline(m: int, n_s: int) -> dict:
     return {"value": dofs / sec, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_s}^3 cells, m={m}, 1 full step (2 half steps) of the same Fourier-mode "
                       f"workload, {sec:.2f} s on {cores} threads",
+            "effective_parallelism": cpu / sec, "cgroup_cpu_quota": quota,
             "cpu_model": model, "single_thread": single}
 
 

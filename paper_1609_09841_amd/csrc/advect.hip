@@ -30,6 +30,7 @@ namespace {
 
 using fused::Cell16;
 using fused::cell_nodes;
+using fused::cell_writing;
 
 constexpr int kThreads = 256;
 
@@ -42,9 +43,9 @@ template <int M>
 __global__ __launch_bounds__(kThreads) void advect_kernel(const double* __restrict__ src, double* __restrict__ dst,
                                                           AxisOp<M> K, uint32_t n, size_t pitch, uint32_t off) {
     constexpr int P = 2 * M, M3 = M * M * M;
-    const uint32_t cell = blockIdx.x * kThreads + threadIdx.x;
-    if (cell >= n * n * n) return;
-    const Cell16 c = cell_nodes(cell, n, off);
+    const uint32_t node = blockIdx.x * kThreads + threadIdx.x;  // new node this lane writes
+    if (node >= n * n * n) return;
+    const Cell16 c = cell_writing(node, n, off);
     double y[M3];
 #pragma unroll
     for (int t = 0; t < M3; ++t) y[t] = 0.0;

@@ -31,6 +31,30 @@ __device__ __forceinline__ Cell16 cell_nodes(uint32_t cell, uint32_t n, uint32_t
     return c;
 }
 
+// The same cell, enumerated by the node it writes: node (i, j, k) of the new
+// grid comes from the cell with lower corner (i - off, j - off, k - off) mod
+// n. Kernels that give consecutive lanes consecutive nodes this way store
+// whole cache lines in both half steps (off = 1 would otherwise shift every
+// store of a wave by one node).
+__device__ __forceinline__ Cell16 cell_writing(uint32_t node, uint32_t n, uint32_t off) {
+    const uint32_t i = node % n, t = node / n, j = t % n, k = t / n;
+    uint32_t xs[2], ys[2], zs[2];
+    if (off) {
+        xs[0] = i ? i - 1 : n - 1, xs[1] = i;
+        ys[0] = j ? j - 1 : n - 1, ys[1] = j;
+        zs[0] = k ? k - 1 : n - 1, zs[1] = k;
+    } else {
+        xs[0] = i, xs[1] = (i + 1 == n) ? 0 : i + 1;
+        ys[0] = j, ys[1] = (j + 1 == n) ? 0 : j + 1;
+        zs[0] = k, zs[1] = (k + 1 == n) ? 0 : k + 1;
+    }
+    Cell16 c;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) c.corner[s] = (zs[s >> 2] * n + ys[(s >> 1) & 1]) * n + xs[s & 1];
+    c.out = node;
+    return c;
+}
+
 // Butterfly of the 8 corner values v[s1 + 2 s2 + 4 s3] of one derivative
 // multi-index: T[t1 + 2 t2 + 4 t3] = sum_s prod_x (t_x ? (s_x ? 1 : -1) : 1) v[s]
 // (t_x = 1: right minus left along x, t_x = 0: right plus left). Parity class

@@ -26,7 +26,7 @@ namespace {
 
 using fused::butterfly8;
 using fused::Cell16;
-using fused::cell_nodes;
+using fused::cell_writing;
 
 constexpr int kThreads = 256;
 
@@ -60,9 +60,9 @@ __global__ __launch_bounds__(kThreads) void fused_valu4_kernel(const double* __r
                                                                size_t pitch, uint32_t off) {
     const uint32_t ncell = n * n * n;
     const uint32_t fo = blockIdx.x & 1;
-    const uint32_t cell = (blockIdx.x >> 1) * kThreads + threadIdx.x;
-    const bool valid = cell < ncell;
-    const Cell16 c = cell_nodes(valid ? cell : 0u, n, off);
+    const uint32_t node = (blockIdx.x >> 1) * kThreads + threadIdx.x;  // new node this lane writes
+    const bool valid = node < ncell;
+    const Cell16 c = cell_writing(valid ? node : 0u, n, off);
     const double* __restrict__ Kf = Kv + (size_t)fo * (128 * 64);
     double acc[8][8];
 #pragma unroll
@@ -165,10 +165,10 @@ struct SmallCols {
 template <int M>
 __device__ __forceinline__ void small_cell(const double* __restrict__ src, double* __restrict__ dst,
                                            const double* __restrict__ Kv, uint32_t n, size_t pitch, uint32_t off,
-                                           uint32_t cell) {
+                                           uint32_t node) {
     constexpr SmallLayout<M> L{};
     constexpr int NO = SmallLayout<M>::NO;
-    const Cell16 c = cell_nodes(cell, n, off);
+    const Cell16 c = cell_writing(node, n, off);
     double acc[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
@@ -182,9 +182,9 @@ __global__ __launch_bounds__(kThreads) void fused_valu_small_kernel(const double
                                                                     double* __restrict__ dst,
                                                                     const double* __restrict__ Kv, uint32_t n,
                                                                     size_t pitch, uint32_t off) {
-    const uint32_t cell = blockIdx.x * kThreads + threadIdx.x;
-    if (cell >= n * n * n) return;
-    small_cell<M>(src, dst, Kv, n, pitch, off, cell);
+    const uint32_t node = blockIdx.x * kThreads + threadIdx.x;
+    if (node >= n * n * n) return;
+    small_cell<M>(src, dst, Kv, n, pitch, off, node);
 }
 
 // Batched: work item = a block of BS cells of one shot (batch_common.h).
@@ -196,9 +196,9 @@ __global__ __launch_bounds__(BS) void fused_valu_small_batch_kernel(const batch:
     const uint32_t g = batch::find_entry(prefix, ng, blockIdx.x);
     const batch::ShotGrid& S = shots[ids[g]];
     const uint32_t n = S.n;
-    const uint32_t cell = (blockIdx.x - prefix[g]) * BS + threadIdx.x;
-    if (cell >= n * n * n) return;
-    small_cell<M>(S.grid[from], S.grid[1 - from], Kv, n, S.pitch, from, cell);
+    const uint32_t node = (blockIdx.x - prefix[g]) * BS + threadIdx.x;
+    if (node >= n * n * n) return;
+    small_cell<M>(S.grid[from], S.grid[1 - from], Kv, n, S.pitch, from, node);
 }
 
 template <int M>
