@@ -16,9 +16,9 @@
 // m = 1, 2 (adjoint_kernel): one lane per (node, input field fi), M^3
 // accumulators; the 8 cells are a runtime loop, classes, class rows and
 // columns are unrolled, so the operator entries are wave-uniform scalar
-// operands. This repeats each cell's transposed contraction at its 8
-// vertices; m = 3 (adjoint_mfma_kernel below) computes it once per cell on
-// the matrix cores and sums the vertex contributions in a second pass.
+// operands. m = 3 (adjoint_mfma_kernel below) butterflies the adjoint values
+// of the 8 neighbouring new nodes first and runs the transposed products on
+// the matrix cores, as many as the forward half step.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -113,65 +113,106 @@ __global__ void inject_kernel(double* __restrict__ lam, const uint32_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// m = 3 on the FP64 matrix cores, scatter form. Per batch of 16 cells of one
-// x-row (the forward kernels' XCD-blocked sweep), the transposed class
-// products G_p = K_p^T Lam_p (128 columns x 16 cells, K = the 16 class rows)
-// run as 8 column tiles x 8 classes x 4 K-steps of v_mfma_f64_16x16x4f64 -
-// as many as the forward half step. The tile rows are ordered so that
-// register r of lane quarter g holds column d = f 64 + (d3 4 + d2) 4 + d1 with
-//   d1 = 2 (T & 1) + (r & 1), d2 = 2 ((T >> 1) & 1) + (r >> 1),
-//   d3 = 2 (g & 1) + (T >> 2), f = g >> 1     (T: tile),
-// so the parity of d, which says which class feeds which butterfly output,
-// depends on (T, r) only. The transposed butterfly then gives the cell's 8
-// vertex contributions e_s[d], stored to E[s][d][cell]; a second kernel sums,
-// per node, the 8 contributions of the cells around it.
+// m = 3 on the FP64 matrix cores, gather form. With U_{p,r}[t] the butterfly
+// of lam_y[p, r] over a node's 8 neighbours (node - s + off, s in {0,1}^3),
+//   U_{p,r}[t] = sum_s sg(t, s) lam_y[p, r](node - s + off),
+// the adjoint at the node is
+//   g[c] = sum_p sum_r K_p[r][c] U_{p,r}[p xor par(c)],
+// the forward kernel's contraction with the roles exchanged: the input
+// columns are the 128 (class p, class row r) pairs of lam (32 K-steps of 4,
+// step T holding class p = T / 4), the accumulators are the 8 parity groups
+// pi of the output columns c (16 columns each: 2 fields x 2x2x2 orders), and
+// group pi takes butterfly output p xor pi. Per batch of 16 nodes of one
+// x-row: 256 v_mfma_f64_16x16x4f64, the neighbour gathers and butterflies of
+// the forward half step, one store of each new value; no scratch.
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kMfWaves = 8;
-constexpr int kAdjOpDoubles = 8 * 8 * 4 * 64;  // [class][tile][K-step][lane]
+constexpr int kAdjOpDoubles = 8 * 32 * 64;  // [group][K-step][lane]
+constexpr int kAdjAhead = 2;
+constexpr int kAdjRing = kAdjAhead + 1;
 
-struct AdjSrcCols {
-    int col[8][4][4];  // [class][K-step][quarter] -> destination column of class row 4 ks + q
-    constexpr AdjSrcCols() : col() {
+// Packed per-lane column table: step T, quarter q reads the lam column of
+// class T / 4, class row 4 (T % 4) + q (7 bits, four steps per word).
+struct AdjColTable {
+    uint32_t w[4][8];
+    constexpr AdjColTable() : w() {
         constexpr AdjLayout<4> L{};
-        for (int p = 0; p < 8; ++p)
-            for (int ks = 0; ks < 4; ++ks)
-                for (int q = 0; q < 4; ++q) col[p][ks][q] = L.row_col[p][4 * ks + q];
+        for (int q = 0; q < 4; ++q)
+            for (int T = 0; T < 32; ++T) w[q][T >> 2] |= (uint32_t)L.row_col[T >> 2][4 * (T & 3) + q] << (8 * (T & 3));
     }
 };
-__constant__ AdjSrcCols kAdjSrcCols = AdjSrcCols();
+__constant__ AdjColTable kAdjColTable = AdjColTable();
 
-__host__ __device__ constexpr int adj_col(int T, int g, int r) {
-    const int d1 = 2 * (T & 1) + (r & 1), d2 = 2 * ((T >> 1) & 1) + (r >> 1), d3 = 2 * (g & 1) + (T >> 2);
+// Column c of logical output row l = 4 g + r of parity group pi (register r of
+// lane quarter g): field g / 2, d_x = pi_x + 2 b_x with b3 = g % 2, b2 = r / 2,
+// b1 = r % 2.
+__host__ __device__ constexpr int adj_out_col(int pi, int g, int r) {
+    const int d1 = (pi & 1) + 2 * (r & 1), d2 = ((pi >> 1) & 1) + 2 * (r >> 1), d3 = (pi >> 2) + 2 * (g & 1);
     return (g >> 1) * 64 + (d3 * 4 + d2) * 4 + d1;
 }
-__host__ __device__ constexpr int adj_par(int T, int r) { return (r & 1) | (((r >> 1) & 1) << 1) | ((T >> 2) << 2); }
 
-// e_s = sum_t sg(t, s) T_t: per axis, s_x = 0 takes T(t_x=0) - T(t_x=1), s_x = 1 the sum.
-__device__ __forceinline__ void butterfly8_T(const double* T, double* e) {
-    double a[8], b[8];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        a[2 * q] = T[2 * q] - T[2 * q + 1];
-        a[2 * q + 1] = T[2 * q] + T[2 * q + 1];
+// The 8 neighbours node - s + off of a node (per axis, periodic), as corners.
+__device__ __forceinline__ fused::Cell16 node_neighbours(uint32_t node, uint32_t n, uint32_t off) {
+    const uint32_t i = node % n, t = node / n, j = t % n, k = t / n;
+    uint32_t xs[2], ys[2], zs[2];
+    if (off) {
+        xs[0] = (i + 1 == n) ? 0 : i + 1, xs[1] = i;
+        ys[0] = (j + 1 == n) ? 0 : j + 1, ys[1] = j;
+        zs[0] = (k + 1 == n) ? 0 : k + 1, zs[1] = k;
+    } else {
+        xs[0] = i, xs[1] = i ? i - 1 : n - 1;
+        ys[0] = j, ys[1] = j ? j - 1 : n - 1;
+        zs[0] = k, zs[1] = k ? k - 1 : n - 1;
     }
+    fused::Cell16 c;
 #pragma unroll
-    for (int s1 = 0; s1 < 2; ++s1)
-#pragma unroll
-        for (int t3 = 0; t3 < 2; ++t3) {
-            const double l = a[s1 + 4 * t3], r = a[s1 + 2 + 4 * t3];
-            b[s1 + 4 * t3] = l - r;
-            b[s1 + 2 + 4 * t3] = l + r;
-        }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        e[k] = b[k] - b[k + 4];
-        e[k + 4] = b[k] + b[k + 4];
-    }
+    for (int s = 0; s < 8; ++s) c.corner[s] = (zs[s >> 2] * n + ys[(s >> 1) & 1]) * n + xs[s & 1];
+    c.out = node;
+    return c;
 }
 
+template <int T>
+__device__ __forceinline__ void adj_load_step(const double* __restrict__ lam, size_t plane, const fused::Cell16& c,
+                                              const uint32_t* packed, double* v) {
+    const double* __restrict__ b = lam + (size_t)((packed[T >> 2] >> (8 * (T & 3))) & 0xFFu) * plane;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = b[c.corner[s]];
+}
+
+template <int T>
+struct AdjSteps {
+    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t plane, const fused::Cell16& c,
+                                               const uint32_t* packed, int lane, const double* sK, d4* acc,
+                                               double (*ring)[8]) {
+        constexpr int p = T >> 2;  // class of this step's lam rows
+        if constexpr (T + kAdjAhead < 32)
+            adj_load_step<T + kAdjAhead>(lam, plane, c, packed, ring[(T + kAdjAhead) % kAdjRing]);
+        double U[8];
+        fused::butterfly8(ring[T % kAdjRing], U);
+        double a[8];
+#pragma unroll
+        for (int pi = 0; pi < 8; ++pi) a[pi] = sK[(pi * 32 + T) * 64 + lane];
+#pragma unroll
+        for (int pi = 0; pi < 8; ++pi) acc[pi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[pi], U[pi ^ p], acc[pi], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (T + 1 < 32) AdjSteps<T + 1>::run(lam, plane, c, packed, lane, sK, acc, ring);
+    }
+};
+
+template <int T>
+struct AdjPrologue {
+    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t plane, const fused::Cell16& c,
+                                               const uint32_t* packed, double (*ring)[8]) {
+        adj_load_step<T>(lam, plane, c, packed, ring[T]);
+        if constexpr (T + 1 < kAdjAhead) AdjPrologue<T + 1>::run(lam, plane, c, packed, ring);
+    }
+};
+
+// Persistent kernel over the XCD-blocked row sweep (fused::sweep_rows), one
+// batch of 16 consecutive nodes per wave and step of the sweep.
 __global__ __launch_bounds__(kMfWaves * 64) void adjoint_mfma_kernel(const double* __restrict__ lam_dst,
-                                                                     double* __restrict__ E,
+                                                                     double* __restrict__ lam_src,
                                                                      const double* __restrict__ KT, uint32_t n,
                                                                      size_t pitch, uint32_t off) {
     __shared__ double sK[kAdjOpDoubles];
@@ -179,61 +220,30 @@ __global__ __launch_bounds__(kMfWaves * 64) void adjoint_mfma_kernel(const doubl
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
+    uint32_t packed[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) packed[k] = kAdjColTable.w[q][k];
     fused::sweep_rows(n, wave, kMfWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
         const uint32_t x = x0 + cl;
         const bool valid = x < n;
-        const uint32_t cell = (z * n + y) * n + (valid ? x : n - 1);
-        const fused::Cell16 c = fused::cell_nodes(cell, n, off);
-        // B operands: Lam_p rows 4 ks + q of this lane's cell (its new node)
-        double lb[8][4];
+        const uint32_t node = (z * n + y) * n + (valid ? x : n - 1);
+        const fused::Cell16 c = node_neighbours(node, n, off);
+        // opaque per batch (keeps the per-lane column bases from being hoisted
+        // out of the sweep, which would pin 64 registers)
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+        for (int w = 0; w < 8; ++w) asm volatile("" : "+v"(packed[w]));
+        d4 acc[8];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) lb[p][ks] = lam_dst[(size_t)kAdjSrcCols.col[p][ks][q] * pitch + c.out];
+        for (int pi = 0; pi < 8; ++pi) acc[pi] = d4{0.0, 0.0, 0.0, 0.0};
+        double ring[kAdjRing][8];
+        AdjPrologue<0>::run(lam_dst, pitch, c, packed, ring);
+        AdjSteps<0>::run(lam_dst, pitch, c, packed, lane, sK, acc, ring);
+        if (!valid) return;
 #pragma unroll
-        for (int T = 0; T < 8; ++T) {
-            d4 acc[8];
+        for (int pi = 0; pi < 8; ++pi)
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
-                acc[p] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks)
-                    acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(sK[((p * 8 + T) * 4 + ks) * 64 + lane], lb[p][ks],
-                                                                  acc[p], 0, 0, 0);
-            }
-            if (valid) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    // butterfly output t is fed by class t xor par(column), par fixed by (T, r)
-                    const int par = adj_par(T, r);
-                    double Tv[8], e[8];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) Tv[t] = acc[t ^ par][r];
-                    butterfly8_T(Tv, e);
-                    const int d = adj_col(T, q, r);
-#pragma unroll
-                    for (int sv = 0; sv < 8; ++sv) E[((size_t)sv * 128 + d) * pitch + cell] = e[sv];
-                }
-            }
-        }
+            for (int r = 0; r < 4; ++r) lam_src[(size_t)adj_out_col(pi, q, r) * pitch + node] = acc[pi][r];
     });
-}
-
-// lam_src[col][node] = sum_s E[s][col][node - s] (periodic), in s order.
-__global__ __launch_bounds__(kThreads) void adjoint_gather_kernel(const double* __restrict__ E,
-                                                                  double* __restrict__ lam_src, uint32_t n,
-                                                                  size_t pitch) {
-    const uint32_t node = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t col = blockIdx.y;
-    if (node >= n * n * n) return;
-    const uint32_t i = node % n, t = node / n, j = t % n, k = t / n;
-    double acc = 0.0;
-#pragma unroll
-    for (int sv = 0; sv < 8; ++sv) {
-        const uint32_t ci = (i + n - (sv & 1)) % n, cj = (j + n - ((sv >> 1) & 1)) % n, ck = (k + n - (sv >> 2)) % n;
-        acc += E[((size_t)sv * 128 + col) * pitch + ((size_t)ck * n + cj) * n + ci];
-    }
-    lam_src[(size_t)col * pitch + node] = acc;
 }
 
 }  // namespace
@@ -241,27 +251,24 @@ __global__ __launch_bounds__(kThreads) void adjoint_gather_kernel(const double* 
 size_t adjoint_mfma_operator_doubles() { return (size_t)kAdjOpDoubles; }
 
 void adjoint_mfma_build_operator(const double* K, double* KT) {
-    // K: canonical [8][16][128]. A operand of (class p, tile T, K-step ks):
-    // lane = i + 16 k, A[i][k] = K_p[4 ks + k][column of logical tile row
-    // 4 (i % 4) + i / 4], whose register is i / 4 in quarter i % 4.
-    for (int p = 0; p < 8; ++p)
-        for (int T = 0; T < 8; ++T)
-            for (int ks = 0; ks < 4; ++ks)
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int i = lane & 15, k = lane >> 4;
-                    const int g = i & 3, r = i >> 2;
-                    KT[((p * 8 + T) * 4 + ks) * 64 + lane] = K[((size_t)p * 16 + 4 * ks + k) * 128 + adj_col(T, g, r)];
-                }
+    // K: canonical [8][16][128]. A operand of (group pi, step T): lane = i + 16 k,
+    // A[i][k] = K_p[4 (T % 4) + k][column of logical row 4 (i % 4) + i / 4 of
+    // group pi], p = T / 4: the MFMA leaves output row i in register i / 4 of
+    // lane quarter i % 4, so register r of quarter g holds logical row 4 g + r.
+    for (int pi = 0; pi < 8; ++pi)
+        for (int T = 0; T < 32; ++T)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = lane & 15, k = lane >> 4, p = T >> 2;
+                KT[((size_t)pi * 32 + T) * 64 + lane] =
+                    K[((size_t)p * 16 + 4 * (T & 3) + k) * 128 + adj_out_col(pi, i & 3, i >> 2)];
+            }
 }
 
-hipError_t launch_adjoint_mfma(const double* lam_dst, double* lam_src, double* E, const double* KT, int n,
-                               size_t pitch, int off, int grid, hipStream_t st) {
+hipError_t launch_adjoint_mfma(const double* lam_dst, double* lam_src, const double* KT, int n, size_t pitch, int off,
+                               int grid, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(adjoint_mfma_kernel, dim3(grid), dim3(kMfWaves * 64), 0, st, lam_dst, E, KT, (uint32_t)n,
-                       pitch, (uint32_t)off);
-    const uint32_t ncell = (uint32_t)n * n * n;
-    hipLaunchKernelGGL(adjoint_gather_kernel, dim3((ncell + kThreads - 1) / kThreads, 128), dim3(kThreads), 0, st,
-                       (const double*)E, lam_src, (uint32_t)n, pitch);
+    hipLaunchKernelGGL(adjoint_mfma_kernel, dim3(grid), dim3(kMfWaves * 64), 0, st, lam_dst, lam_src, KT,
+                       (uint32_t)n, pitch, (uint32_t)off);
     return hipGetLastError();
 }
 

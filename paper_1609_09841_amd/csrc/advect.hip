@@ -33,6 +33,11 @@ using fused::cell_nodes;
 using fused::cell_writing;
 
 constexpr int kThreads = 256;
+// At m = 3 the 64 accumulators and the 8-value x1-line fit in about 200
+// registers; left alone the compiler takes all 256 (one wave per SIMD, no
+// latency hiding), so the bound asks for two.
+template <int M>
+constexpr int kMinWaves = M == 4 ? 2 : 1;
 
 template <int M>
 struct AxisOp {
@@ -40,7 +45,7 @@ struct AxisOp {
 };
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void advect_kernel(const double* __restrict__ src, double* __restrict__ dst,
+__global__ __launch_bounds__(kThreads, kMinWaves<M>) void advect_kernel(const double* __restrict__ src, double* __restrict__ dst,
                                                           AxisOp<M> K, uint32_t n, size_t pitch, uint32_t off) {
     constexpr int P = 2 * M, M3 = M * M * M;
     const uint32_t node = blockIdx.x * kThreads + threadIdx.x;  // new node this lane writes
@@ -108,7 +113,7 @@ struct EvolveOp {
 };
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void advect_evolve_kernel(const double* __restrict__ R,
+__global__ __launch_bounds__(kThreads, kMinWaves<M>) void advect_evolve_kernel(const double* __restrict__ R,
                                                                  double* __restrict__ dst, EvolveOp<M> E,
                                                                  uint32_t n, size_t pitch, uint32_t off) {
     constexpr int P = 2 * M, M3 = M * M * M;

@@ -54,7 +54,6 @@ struct hermite_ctx {
     uint32_t* d_rec = nullptr;                // receiver nodes (flat primal indices)
     uint32_t nrec = 0;
     void* Kadj = nullptr;                     // adjoint operator (canonical, or the m = 3 matrix-core layout)
-    double* E = nullptr;                      // m = 3 adjoint scratch: 8 vertices x 128 columns per cell
     double* d_partial = nullptr;              // source-gradient block partials
     uint32_t partial_cap = 0;                 // doubles in d_partial
     bool adjoint = false;                     // grids hold an adjoint state
@@ -102,7 +101,6 @@ void free_all(hermite_ctx* ctx) {
     if (ctx->d_source_scal) { (void)hipFree(ctx->d_source_scal); ctx->d_source_scal = nullptr; }
     if (ctx->d_rec) { (void)hipFree(ctx->d_rec); ctx->d_rec = nullptr; }
     if (ctx->Kadj) { (void)hipFree(ctx->Kadj); ctx->Kadj = nullptr; }
-    if (ctx->E) { (void)hipFree(ctx->E); ctx->E = nullptr; }
     if (ctx->d_partial) { (void)hipFree(ctx->d_partial); ctx->d_partial = nullptr; }
     if (ctx->own_stream && ctx->stream) { (void)hipStreamDestroy(ctx->stream); ctx->stream = nullptr; }
 }
@@ -498,7 +496,7 @@ namespace {
 hipError_t adjoint_half(hermite_ctx* ctx, const double* lam_dst, double* lam_src, int off) {
     if (ctx->m == 3) {
         const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
-        return hermite::launch_adjoint_mfma(lam_dst, lam_src, ctx->E, (const double*)ctx->Kadj, ctx->n, ctx->pitch,
+        return hermite::launch_adjoint_mfma(lam_dst, lam_src, (const double*)ctx->Kadj, ctx->n, ctx->pitch,
                                             off, grid, ctx->stream);
     }
     return hermite::launch_adjoint(ctx->m, lam_dst, lam_src, (const double*)ctx->Kadj, ctx->n, ctx->pitch, off,
@@ -528,7 +526,6 @@ int hermite_adjoint_init(hermite_ctx* ctx, const void* lam_u_dev, const void* la
             std::vector<double> KT(hermite::adjoint_mfma_operator_doubles());
             hermite::adjoint_mfma_build_operator(K.data(), KT.data());
             K.swap(KT);
-            HCHECK(ctx, hipMalloc(&ctx->E, (size_t)1024 * ctx->pitch * sizeof(double)), "hipMalloc(adjoint scratch)");
         }
         HCHECK(ctx, hipMalloc(&ctx->Kadj, K.size() * sizeof(double)), "hipMalloc(adjoint operator)");
         HCHECK(ctx, hipMemcpy(ctx->Kadj, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice),

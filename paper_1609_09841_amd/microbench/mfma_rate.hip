@@ -2,7 +2,9 @@
 // built on: FP64 / FP32 / BF16 matrix-core products and FP64 vector FMAs, each
 // as 8 (or 16) independent accumulation chains per wave with no memory
 // traffic, 4 waves per SIMD. The mixed case runs matrix-core and vector waves
-// side by side to see whether the two FP64 paths share execution resources.
+// side by side to see whether the two FP64 paths share execution resources;
+// the last cases take the vector FMA's second factor from memory through
+// scalar loads.
 // Build: hipcc --offload-arch=gfx950 -O3 -o mfma_rate mfma_rate.hip
 #include <hip/hip_runtime.h>
 #include <cstdio>
@@ -105,6 +107,57 @@ __global__ __launch_bounds__(256) void k(double* out, int iters) {
     }
 }
 
+// FP64 vector FMAs whose second factor is a wave-uniform operator entry read
+// from memory (scalar loads into scalar registers), as a vector-ALU
+// contraction with a shared operator needs: 64 accumulators per lane, per
+// column 64 FMAs with the column's 64 entries (operator slice of opc columns,
+// cycled) plus 8 multiplies that keep the per-lane inputs live.
+__global__ __launch_bounds__(256) void kop(const double* __restrict__ op, int opc, double* __restrict__ out,
+                                           int iters) {
+    const int lane = threadIdx.x & 63;
+    double acc[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) acc[r] = lane * 1e-3 + r;
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = 1.0 - (lane + k) * 1e-4;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll 1
+        for (int c = 0; c < 128; ++c) {
+            const double* __restrict__ o = op + (size_t)(c % opc) * 64;
+#pragma unroll
+            for (int r = 0; r < 64; ++r) acc[r] = __builtin_fma(o[r], x[r & 7], acc[r]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = x[k] * 0.999999;
+        }
+    }
+    double s = 0;
+#pragma unroll
+    for (int r = 0; r < 64; ++r) s += acc[r];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+void run_scalar_operand(int opc) {
+    const int blocks = 512, threads = 256, iters = 40;
+    double *op = nullptr, *out = nullptr;
+    if (hipMalloc(&op, 128 * 64 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&out, (size_t)blocks * threads * sizeof(double)) != hipSuccess)
+        std::exit(1);
+    if (hipMemset(op, 0, 128 * 64 * sizeof(double)) != hipSuccess) std::exit(1);
+    hipLaunchKernelGGL(kop, dim3(blocks), dim3(threads), 0, 0, op, opc, out, 2);
+    hipEvent_t e0, e1; hipEventCreate(&e0); hipEventCreate(&e1);
+    hipEventRecord(e0);
+    hipLaunchKernelGGL(kop, dim3(blocks), dim3(threads), 0, 0, op, opc, out, iters);
+    hipEventRecord(e1); hipEventSynchronize(e1);
+    if (hipGetLastError() != hipSuccess) std::exit(1);
+    float ms; hipEventElapsedTime(&ms, e0, e1);
+    const double fma = (double)blocks * threads * iters * 128 * 64;
+    printf("v_fma_f64, scalar operand, operator %6d B: %8.3f ms  %8.2f TFLOP/s (FMAs only)\n", opc * 64 * 8, ms,
+           2 * fma / ms / 1e9);
+    hipFree(op);
+    hipFree(out);
+}
+
 template <int KIND>
 void run(const char* name, double flops_per_inst_wave, int insts_per_iter) {
     int dev = 0, cus = 0;
@@ -143,5 +196,7 @@ int main() {
     // or their sum (shared units). Reported TFLOP/s counts both kinds.
     run<4>("mixed f64 mfma+valu waves", 0.5 * (2.0 * 16 * 16 * 4 * 8) + 0.5 * (2.0 * 64 * 128), 1);
     run<5>("mfma_f32_16x16x32_bf16", 2.0 * 16 * 16 * 32, 8);
+    run_scalar_operand(2);     // 1 KB: always in the scalar cache
+    run_scalar_operand(128);   // 64 KB streamed per wave
     return 0;
 }
