@@ -373,7 +373,8 @@ int hermite_batch_create(int n_shots, const hermite_shot* shots, double cfl, dou
         std::vector<unsigned char> Kdev;
         if (m < 3) {
             Kdev.resize(hermite::valu_small_operator_doubles(m) * sizeof(double));
-            hermite::valu_small_build_operators(m, K.data(), (double*)Kdev.data());
+            if (!hermite::valu_small_build_operators(m, K.data(), (double*)Kdev.data()))
+                return bail(bfail(b, HERMITE_EUNSUPPORTED, "class operator has a nonzero entry the kernel skips"));
         } else if (o.precision != HERMITE_PREC_FP64) {
             Kdev.resize(hermite::mixed_operator_bytes(o.precision));
             hermite::mixed_build_operators(o.precision, K.data(), Kdev.data());

@@ -283,7 +283,8 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         hermite::valu4_build_operators(K.data(), (double*)Kdev.data());
     } else {
         Kdev.resize(hermite::valu_small_operator_doubles(m) * sizeof(double));
-        hermite::valu_small_build_operators(m, K.data(), (double*)Kdev.data());
+        if (!hermite::valu_small_build_operators(m, K.data(), (double*)Kdev.data()))
+            return bail(fail(ctx, HERMITE_EUNSUPPORTED, "class operator has a nonzero entry the kernel skips"));
     }
     if (!Kdev.empty()) {
         e = hipMalloc(&ctx->K, Kdev.size());

@@ -111,7 +111,8 @@ struct SmallLayout {
     int out_class[NO];    // class of output slot o
     int out_j[NO];        // destination row fo * M3 + (j3 M + j2) M + j1 of slot o
     int out_row[NO];      // row of slot o in its class operator (canonical order)
-    constexpr SmallLayout() : col(), out_class(), out_j(), out_row() {
+    bool zero[NC][NO];    // entry (column step C, slot o) vanishes for every time step
+    constexpr SmallLayout() : col(), out_class(), out_j(), out_row(), zero() {
         int k = 0;
         for (int s = 3 * (M - 1); s >= 0; --s)
             for (int f = 1; f >= 0; --f)
@@ -133,6 +134,16 @@ struct SmallLayout {
                             out_row[o] = fo * nof + (o3 * n2 + o2) * n1 + o1;
                             const int j1 = p1 + 2 * o1, j2 = p2 + 2 * o2, j3 = p3 + 2 * o3;
                             out_j[o] = fo * M3 + (j3 * M + j2) * M + j1;
+                            // Along an axis with even class parity, new order
+                            // j_x = 2 takes nothing from input order d_x = 0: the
+                            // even part of the 1D interpolant has no such term and
+                            // the evolution lowers orders in steps of two.
+                            for (int c = 0; c < NC; ++c) {
+                                const int dd = col[c] % M3;
+                                const int d1 = dd % M, d2 = (dd / M) % M, d3 = dd / (M * M);
+                                zero[c][o] = (p1 == 0 && o1 == 1 && d1 == 0) || (p2 == 0 && o2 == 1 && d2 == 0) ||
+                                             (p3 == 0 && o3 == 1 && d3 == 0);
+                            }
                             ++o;
                         }
         }
@@ -157,7 +168,8 @@ struct SmallCols {
         butterfly8(v, T);
         const double* __restrict__ kk = Kv + C * NO;
 #pragma unroll
-        for (int o = 0; o < NO; ++o) acc[o] = __builtin_fma(kk[o], T[L.out_class[o] ^ par], acc[o]);
+        for (int o = 0; o < NO; ++o)
+            if (!L.zero[C][o]) acc[o] = __builtin_fma(kk[o], T[L.out_class[o] ^ par], acc[o]);
         if constexpr (C + 1 < SmallLayout<M>::NC) SmallCols<M, C + 1>::run(src, pitch, cc, Kv, acc);
     }
 };
@@ -219,22 +231,28 @@ hipError_t launch_small_batch(int bs, const batch::ShotGrid* shots, const uint32
 }
 
 template <int M>
-void small_build(const double* K, double* Kv) {
+bool small_build(const double* K, double* Kv) {
     constexpr SmallLayout<M> L{};
     constexpr int NO = SmallLayout<M>::NO, NC = SmallLayout<M>::NC;
     const int no0 = (M + 1) / 2, RM = 2 * no0 * no0 * no0;
+    bool ok = true;
     for (int c = 0; c < NC; ++c)
-        for (int o = 0; o < NO; ++o)
-            Kv[(size_t)c * NO + o] = K[((size_t)L.out_class[o] * RM + L.out_row[o]) * NC + L.col[c]];
+        for (int o = 0; o < NO; ++o) {
+            const double k = K[((size_t)L.out_class[o] * RM + L.out_row[o]) * NC + L.col[c]];
+            Kv[(size_t)c * NO + o] = k;
+            ok = ok && (!L.zero[c][o] || k == 0.0);
+        }
+    return ok;
 }
 
 }  // namespace
 
 size_t valu_small_operator_doubles(int m) { return (size_t)(2 * (m + 1) * (m + 1) * (m + 1)) * (2 * (m + 1) * (m + 1) * (m + 1)); }
 
-void valu_small_build_operators(int m, const double* K, double* Kv) {
-    if (m == 1) small_build<2>(K, Kv);
-    if (m == 2) small_build<3>(K, Kv);
+bool valu_small_build_operators(int m, const double* K, double* Kv) {
+    if (m == 1) return small_build<2>(K, Kv);
+    if (m == 2) return small_build<3>(K, Kv);
+    return false;
 }
 
 hipError_t launch_fused_valu_small(int m, const double* src, double* dst, const double* Kv, int n, size_t pitch,
