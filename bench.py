@@ -107,6 +107,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched point-source leg")
     ap.add_argument("--no-advection", action="store_true", help="skip the advection leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint-gradient leg")
+    ap.add_argument("--no-slab", action="store_true", help="skip the one-slab (sharded share) leg")
     ap.add_argument("--gradient-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -298,6 +299,57 @@ def advection_leg(B, torch, I, n: int = 150, steps: int = 200, warmup: int = 1) 
                         "paper_time_s": PAPER_ADVECTION_S[m], "paper_two_kernel_time_s": PAPER_ADVECTION_TWO_S[m]}
         del u0
         torch.cuda.empty_cache()
+    return out
+
+
+def slab_leg(B, torch, I, n: int = 128, nz: int = 16, half_steps: int = 40) -> dict:
+    """One device's share of the headline grid cut into z-slabs (n x n x nz
+    cells of the n^3 grid, m = 3, fused FP64 on the matrix cores): half steps
+    of the slab kernel alone, and with the one-plane halo copy before each
+    (here a copy of the slab's own boundary plane, the same bytes a peer copy
+    would move). No multi-device figure: the exchange between devices and its
+    overlap are not run here."""
+    m, M = 3, 4
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    u0, ut0 = I.fourier_initial(n, m)
+    u0 = u0.numpy()[:, :, :, :nz].copy()
+    ut0 = ut0.numpy()[:, :, :, :nz].copy()
+    out = {"workload": f"z-slab {n} x {n} x {nz} cells of the {n}^3 m=3 grid (1/{n // nz} of it), fused FP64"}
+    with B.Slab(n, nz, stream=stream) as sl:
+        sl.set_initial(u0, ut0)
+
+        def run(k, exchange, compute=True):
+            nxt = B.HERMITE_SLAB_PRIMAL_HALO
+            for i in range(k):
+                if exchange:
+                    if nxt == B.HERMITE_SLAB_PRIMAL_HALO:
+                        sl.copy_plane_from(nxt, sl, B.HERMITE_SLAB_PRIMAL_FIRST)
+                    else:
+                        sl.copy_plane_from(nxt, sl, B.HERMITE_SLAB_DUAL_LAST)
+                if compute:
+                    nxt = sl.half_step()
+                else:
+                    nxt = B.HERMITE_SLAB_DUAL_HALO if i % 2 == 0 else B.HERMITE_SLAB_PRIMAL_HALO
+
+        res = {}
+        for name, exchange, compute in (("kernel_only", False, True), ("with_plane_copy", True, True),
+                                        ("plane_copy_only", True, False)):
+            run(2, exchange, compute)
+            sl.sync()
+            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            run(half_steps, exchange, compute)
+            end.record(stream)
+            end.synchronize()
+            res[name] = start.elapsed_time(end) / half_steps
+        sl.sync()
+    dof = 2 * M ** 3 * n * n * nz
+    plane_bytes = 2 * M ** 3 * n * n * 8
+    out.update({"ms_per_half_step": res["kernel_only"], "ms_per_half_step_with_plane_copy": res["with_plane_copy"],
+                "value": dof / (res["kernel_only"] / 1e3), "unit": "DOF-updates/s",
+                "plane_bytes": plane_bytes, "plane_copy_ms": res["plane_copy_only"],
+                "plane_copy_GBps_on_device": plane_bytes / (res["plane_copy_only"] / 1e3) / 1e9})
     return out
 
 
@@ -498,6 +550,8 @@ def main():
         out["batch"] = batch_leg(B, torch, I, steps=args.batch_steps)
     if not args.no_gradient:
         out["gradient"] = gradient_leg(B, torch, I, steps=args.gradient_steps)
+    if not args.no_slab and m == 3:
+        out["slab"] = slab_leg(B, torch, I, n=args.n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_n)
     print(json.dumps(out), flush=True)

@@ -319,6 +319,62 @@ void hermite_batch_destroy(hermite_batch *b);
  * hermite_batch_create when b is NULL. Never NULL. */
 const char *hermite_batch_last_error(const hermite_batch *b);
 
+/* ------------------------------------------------------------------------
+ * One z-slab of a periodic grid sharded over devices (the grid of Sec. 2
+ * cut into slabs of whole cell planes; one slab per device). A slab owns
+ * the node planes z0 .. z0+nz-1 of both grids and updates them with the
+ * fused m = 3 FP64 half step (Sec. 3.3) on the matrix cores. The primal ->
+ * dual half step reads one primal plane it does not own (z0+nz, the first
+ * plane of the slab above); the dual -> primal half step one dual plane
+ * (z0-1, the last plane of the slab below). The caller moves those planes
+ * between half steps (peer copies, RCCL send/recv, or, for a slab holding
+ * the whole grid, a copy within the slab), reading and writing the device
+ * planes that hermite_slab_plane names. No collectives are made here.
+ *
+ * A plane is 2 (m+1)^3 rows of n^2 doubles (row r = column r of the grid
+ * layout: field, then derivative multi-index, as hermite_set_initial),
+ * consecutive rows `pitch_bytes` apart, each row [j][i] with i fastest.
+ * Errors: as hermite_create; options other than FP64, fused, wave equation,
+ * m = 3 give HERMITE_EUNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+typedef struct hermite_slab hermite_slab; /* opaque; owns its device memory */
+
+#define HERMITE_SLAB_PRIMAL_FIRST 0 /* own primal plane z0: the slab below reads it */
+#define HERMITE_SLAB_PRIMAL_HALO 1  /* primal plane z0+nz: fill before a primal -> dual half step */
+#define HERMITE_SLAB_DUAL_LAST 2    /* own dual plane z0+nz-1: the slab above reads it */
+#define HERMITE_SLAB_DUAL_HALO 3    /* dual plane z0-1: fill before a dual -> primal half step */
+
+/* n_cells: cells per side in x and y (2 .. 1290); nz: cell planes of this
+ * slab, 1 <= nz, n_cells^2 (nz+1) < 2^31; cfl, c, opt as hermite_create. */
+int hermite_slab_create(int n_cells, int nz, int m, double cfl, double c, const hermite_options *opt,
+                        hermite_slab **out);
+/* Host arrays of the slab's own planes: u, ut each (m+1)^3 nz n^2 doubles,
+ * [d3][d2][d1][k][j][i] with k = 0 .. nz-1 the planes z0 .. z0+nz-1;
+ * synchronous; resets the time to 0 and the next half step to primal -> dual. */
+int hermite_slab_set_initial(hermite_slab *s, const double *u, const double *ut);
+/* Device address of one of the four exchange planes (HERMITE_SLAB_*) and
+ * the row stride in bytes. The addresses stay valid until destroy. */
+int hermite_slab_plane(hermite_slab *s, int which, void **dev, size_t *pitch_bytes);
+/* Enqueue one half step on the slab's stream: primal -> dual when the slab
+ * has taken an even number of half steps, dual -> primal otherwise. The
+ * halo plane it reads must be filled (stream-ordered) before the call.
+ * Returns in *next_halo (if not NULL) the HERMITE_SLAB_*_HALO plane the
+ * following half step reads. */
+int hermite_slab_half_step(hermite_slab *s, int *next_halo);
+/* After an even number of half steps: the slab's own planes (layout as
+ * set_initial; either pointer may be NULL) and t = full steps * dt;
+ * synchronous. HERMITE_ESTATE after an odd number. */
+int hermite_slab_gather(hermite_slab *s, double *u, double *ut, double *t_out);
+/* Copy plane `src_which` of slab `src` into plane `dst_which` of `dst`
+ * (e.g. PRIMAL_FIRST of the slab above into PRIMAL_HALO of this one), as
+ * one 2-D copy enqueued on dst's stream; the slabs may sit on different
+ * devices (a peer copy). The plane of src must be complete when the copy
+ * runs: same stream, or src synchronised. */
+int hermite_slab_copy_plane(hermite_slab *dst, int dst_which, hermite_slab *src, int src_which);
+int hermite_slab_sync(hermite_slab *s);
+void hermite_slab_destroy(hermite_slab *s);
+const char *hermite_slab_last_error(const hermite_slab *s);
+
 #ifdef __cplusplus
 }
 #endif

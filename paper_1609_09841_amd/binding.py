@@ -31,6 +31,10 @@ HERMITE_KERNEL_MFMA = 1
 HERMITE_KERNEL_VALU = 2
 HERMITE_EQ_WAVE = 0
 HERMITE_EQ_ADVECTION = 1
+HERMITE_SLAB_PRIMAL_FIRST = 0
+HERMITE_SLAB_PRIMAL_HALO = 1
+HERMITE_SLAB_DUAL_LAST = 2
+HERMITE_SLAB_DUAL_HALO = 3
 EQUATIONS = {"wave": HERMITE_EQ_WAVE, "advection": HERMITE_EQ_ADVECTION}
 KERNELS = {"auto": HERMITE_KERNEL_AUTO, "mfma": HERMITE_KERNEL_MFMA, "valu": HERMITE_KERNEL_VALU}
 
@@ -46,6 +50,9 @@ EXPORTS = (
     "hermite_batch_gather", "hermite_batch_sync", "hermite_batch_tuning", "hermite_batch_destroy",
     "hermite_batch_last_error", "hermite_set_receivers", "hermite_set_source_series", "hermite_step_record",
     "hermite_adjoint_init", "hermite_adjoint_step", "hermite_adjoint_gather", "hermite_state_finite",
+    "hermite_slab_create", "hermite_slab_set_initial", "hermite_slab_plane", "hermite_slab_half_step",
+    "hermite_slab_gather", "hermite_slab_copy_plane", "hermite_slab_sync", "hermite_slab_destroy",
+    "hermite_slab_last_error",
 )
 
 
@@ -172,6 +179,24 @@ def load(path: str = LIB_PATH):
     lib.hermite_batch_destroy.restype = None
     lib.hermite_batch_last_error.argtypes = [vp]
     lib.hermite_batch_last_error.restype = ctypes.c_char_p
+    lib.hermite_slab_create.argtypes = [ip, ip, ip, ctypes.c_double, ctypes.c_double, opt_p, ctypes.POINTER(vp)]
+    lib.hermite_slab_create.restype = ip
+    lib.hermite_slab_set_initial.argtypes = [vp, dp, dp]
+    lib.hermite_slab_set_initial.restype = ip
+    lib.hermite_slab_plane.argtypes = [vp, ip, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
+    lib.hermite_slab_plane.restype = ip
+    lib.hermite_slab_half_step.argtypes = [vp, ctypes.POINTER(ip)]
+    lib.hermite_slab_half_step.restype = ip
+    lib.hermite_slab_gather.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_double)]
+    lib.hermite_slab_gather.restype = ip
+    lib.hermite_slab_copy_plane.argtypes = [vp, ip, vp, ip]
+    lib.hermite_slab_copy_plane.restype = ip
+    lib.hermite_slab_sync.argtypes = [vp]
+    lib.hermite_slab_sync.restype = ip
+    lib.hermite_slab_destroy.argtypes = [vp]
+    lib.hermite_slab_destroy.restype = None
+    lib.hermite_slab_last_error.argtypes = [vp]
+    lib.hermite_slab_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -483,3 +508,86 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# --- z-slabs of a sharded grid ---------------------------------------------
+
+def hermite_slab_last_error(sl=None) -> str:
+    return load().hermite_slab_last_error(sl).decode(errors="replace")
+
+
+def _scheck(rc: int, sl=None):
+    if rc != HERMITE_OK:
+        raise HermiteError(rc, hermite_slab_last_error(sl))
+
+
+class Slab:
+    """One hermite_slab: the node planes z0 .. z0+nz-1 of a periodic n x n x N
+    grid (m = 3, fused FP64 on the matrix cores). Host arrays are numpy
+    float64 of shape (M, M, M, nz, n, n). The caller fills the halo plane a
+    half step reads (plane(which) gives its device address and row stride)."""
+
+    def __init__(self, n: int, nz: int, m: int = 3, cfl: float = 0.5, c: float = 1.0, *,
+                 evolution: str = "taylor", q: int = 0, rk_substeps: int = 1, stream=None):
+        lib = load()
+        o = hermite_default_options()
+        o.evolution = EVOLUTIONS[evolution]
+        o.q = int(q)
+        o.rk_substeps = int(rk_substeps)
+        if stream is not None:
+            o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        h = ctypes.c_void_p()
+        _scheck(lib.hermite_slab_create(int(n), int(nz), int(m), float(cfl), float(c), ctypes.byref(o),
+                                        ctypes.byref(h)), None)
+        self._s, self._lib = h, lib
+        self.n, self.nz, self.m = int(n), int(nz), int(m)
+        self.rows = 2 * (m + 1) ** 3
+        self._stream = stream
+
+    def set_initial(self, u, ut):
+        size = (self.m + 1) ** 3 * self.nz * self.n ** 2
+        a = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        b = np.ascontiguousarray(np.asarray(ut, dtype=np.float64)).ravel()
+        assert a.size == size and b.size == size
+        _scheck(self._lib.hermite_slab_set_initial(self._s, _dptr(a), _dptr(b)), self._s)
+
+    def plane(self, which: int):
+        """(device address, row stride in bytes) of a HERMITE_SLAB_* plane:
+        2 (m+1)^3 rows of n^2 doubles."""
+        p, pitch = ctypes.c_void_p(), ctypes.c_size_t()
+        _scheck(self._lib.hermite_slab_plane(self._s, int(which), ctypes.byref(p), ctypes.byref(pitch)), self._s)
+        return p.value, pitch.value
+
+    def half_step(self) -> int:
+        """Enqueue one half step; returns the HERMITE_SLAB_*_HALO plane the next one reads."""
+        nxt = ctypes.c_int()
+        _scheck(self._lib.hermite_slab_half_step(self._s, ctypes.byref(nxt)), self._s)
+        return nxt.value
+
+    def gather(self):
+        M = self.m + 1
+        u = np.empty((M, M, M, self.nz, self.n, self.n))
+        ut = np.empty_like(u)
+        t = ctypes.c_double()
+        _scheck(self._lib.hermite_slab_gather(self._s, _dptr(u), _dptr(ut), ctypes.byref(t)), self._s)
+        return u, ut, t.value
+
+    def copy_plane_from(self, which: int, src: "Slab", src_which: int):
+        """Fill plane `which` of this slab from plane `src_which` of `src`
+        (hermite_slab_copy_plane: ordered on this slab's stream)."""
+        _scheck(self._lib.hermite_slab_copy_plane(self._s, int(which), src._s, int(src_which)), self._s)
+
+    def sync(self):
+        _scheck(self._lib.hermite_slab_sync(self._s), self._s)
+
+    def close(self):
+        if getattr(self, "_s", None) is not None:
+            self._lib.hermite_slab_destroy(self._s)
+            self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+

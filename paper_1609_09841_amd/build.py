@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhermite.so")
-SOURCES = ["capi.cpp", "batch.cpp", "host_common.cpp", "constants.cpp", "kernels.hip", "fused_mfma.hip", "fused_mixed.hip", "fused_valu.hip", "source.hip", "advect.hip", "adjoint.hip"]
+SOURCES = ["capi.cpp", "batch.cpp", "slab.cpp", "host_common.cpp", "constants.cpp", "kernels.hip", "fused_mfma.hip", "fused_mixed.hip", "fused_valu.hip", "source.hip", "advect.hip", "adjoint.hip"]
 ARCH = os.environ.get("HERMITE_ARCH", "gfx950")
 
 

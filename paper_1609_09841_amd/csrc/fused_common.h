@@ -55,6 +55,23 @@ __device__ __forceinline__ Cell16 cell_writing(uint32_t node, uint32_t n, uint32
     return c;
 }
 
+// Cell of a z-slab of a periodic grid (x and y periodic, buffer planes k and
+// k + 1 in z, no wrap): lower corner (i, j, k); it writes node (i + off,
+// j + off) mod n on buffer plane k + 1 - off. A slab holds nz + 1 node planes
+// per grid: the primal grid its own planes 0 .. nz-1 and, as plane nz, the
+// first primal plane of the slab above; the dual grid, as plane 0, the last
+// dual plane of the slab below and its own planes as 1 .. nz. Both half steps
+// then update the cells on buffer planes 0 .. nz-1.
+__device__ __forceinline__ Cell16 slab_cell_nodes(uint32_t i, uint32_t j, uint32_t k, uint32_t n, uint32_t off) {
+    const uint32_t i1 = (i + 1 == n) ? 0 : i + 1, j1 = (j + 1 == n) ? 0 : j + 1;
+    Cell16 c;
+    const uint32_t xs[2] = {i, i1}, ys[2] = {j, j1}, zs[2] = {k, k + 1};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) c.corner[s] = (zs[s >> 2] * n + ys[(s >> 1) & 1]) * n + xs[s & 1];
+    c.out = ((k + 1 - off) * n + (off ? j1 : j)) * n + (off ? i1 : i);
+    return c;
+}
+
 // Butterfly of the 8 corner values v[s1 + 2 s2 + 4 s3] of one derivative
 // multi-index: T[t1 + 2 t2 + 4 t3] = sum_s prod_x (t_x ? (s_x ? 1 : -1) : 1) v[s]
 // (t_x = 1: right minus left along x, t_x = 0: right plus left). Parity class
@@ -101,6 +118,25 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
     const uint32_t yy = w % BY, zz = w / BY;
     const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
     const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
+    const uint32_t nbx = (n + 15) / 16;
+    for (uint32_t it = 0; it < nyb * ngr; ++it) {
+        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+        if (y >= n || z >= z1) continue;
+        for (uint32_t bx = wave; bx < nbx; bx += waves) f(bx * 16, y, z);
+    }
+}
+
+// The same sweep over the rows (y, k) of a slab of nz cell planes: each XCD
+// owns nz/8 planes (a thin slab leaves some XCDs fewer), and the block of
+// rows its workgroups run together is at most as deep as its planes.
+template <class F>
+__device__ __forceinline__ void sweep_rows_slab(uint32_t n, uint32_t nz, int wave, int waves, F&& f) {
+    const uint32_t wpx = gridDim.x / 8;
+    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t z0 = xcd * nz / 8, z1 = (xcd + 1) * nz / 8, pz = z1 - z0;
+    const uint32_t BZ = (wpx % 4 == 0 && pz >= 4) ? 4 : (wpx % 2 == 0 && pz >= 2) ? 2 : 1, BY = wpx / BZ;
+    const uint32_t yy = w % BY, zz = w / BY;
+    const uint32_t nyb = (n + BY - 1) / BY, ngr = (pz + BZ - 1) / BZ;
     const uint32_t nbx = (n + 15) / 16;
     for (uint32_t it = 0; it < nyb * ngr; ++it) {
         const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;

@@ -112,6 +112,9 @@ __constant__ ColTable kColTable = ColTable();
 // One batch: the 16 neighbouring cells of row (y, z) whose new nodes are
 // x0 .. x0+15 (lower corners x0 - off .., periodic); lanes past the end of
 // the row compute a copy of the last cell and store nothing.
+// SLAB: z is a buffer plane of a slab (fused::slab_cell_nodes) instead of a
+// plane of the periodic cube.
+template <bool SLAB = false>
 __device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t plane,
                                           uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
                                           int cl, int q, uint32_t* packed, const double* sK) {
@@ -120,7 +123,12 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     // lane cl produces new node x0 + cl of row (y + off, z + off): the cell's
     // lower corner is x - off, so that the stores of a batch fill whole
     // 128-byte lines also in the dual -> primal half step
-    const Cell16 c = cell_nodes((z * n + y) * n + (valid ? (x + n - off) % n : n - 1), n, off);
+    const uint32_t cx = valid ? (x + n - off) % n : n - 1;
+    Cell16 c;
+    if constexpr (SLAB)
+        c = fused::slab_cell_nodes(cx, y, z, n, off);
+    else
+        c = cell_nodes((z * n + y) * n + cx, n, off);
     // Opaque per batch: without this the 32 per-lane column base addresses
     // are hoisted out of the batch loop and pin 64 registers.
 #pragma unroll
@@ -162,6 +170,25 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* _
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
     fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
         run_batch(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
+    });
+}
+
+// One z-slab of a periodic grid sharded over GPUs: the cells on buffer planes
+// 0 .. nz-1 (fused::slab_cell_nodes), the same per-cell arithmetic.
+__global__ __launch_bounds__(kWaves * 64) void fused_mfma_slab_kernel(const double* __restrict__ src,
+                                                                      double* __restrict__ dst,
+                                                                      const double* __restrict__ Kperm, uint32_t n,
+                                                                      uint32_t nz, size_t pitch, uint32_t off) {
+    __shared__ double sK[kOpDoubles];
+    for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = Kperm[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    uint32_t packed[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
+    fused::sweep_rows_slab(n, nz, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
+        run_batch<true>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
     });
 }
 
@@ -217,6 +244,14 @@ void mfma_permute_operators(const double* K, double* Kperm) {
                 const int i = lane & 15, row = 4 * (i & 3) + (i >> 2);
                 Kperm[((size_t)p * 32 + t) * 64 + lane] = K[((size_t)p * 16 + row) * 128 + S.col[t][lane >> 4]];
             }
+}
+
+hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* Kperm, int n, int nz, size_t pitch,
+                                  int off, int grid, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0 || nz < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fused_mfma_slab_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Kperm, (uint32_t)n,
+                       (uint32_t)nz, pitch, (uint32_t)off);
+    return hipGetLastError();
 }
 
 hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm, int n, size_t pitch, int off,

@@ -27,6 +27,11 @@ hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm
                              int grid, hipStream_t st);
 void mfma_permute_operators(const double* K, double* Kperm);
 size_t mfma_operator_doubles();
+// One z-slab of nz cell planes of a periodic n x n x (shards * nz) grid:
+// src and dst hold nz + 1 node planes of n^2 nodes per column (the slab
+// layout of fused::slab_cell_nodes); off as launch_fused_mfma.
+hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* Kperm, int n, int nz, size_t pitch,
+                                  int off, int grid, hipStream_t st);
 
 // Same fused FP64 half step for m = 3 on the vector ALUs: one lane per cell
 // and output field, operator entries as scalar operands. Kv:

@@ -194,3 +194,30 @@ def test_advection_options_validated(field, value, code):
     setattr(o, field, value)
     rc, h = B.hermite_create(8, 3, 0.5, 1.0, o)
     assert rc == code and h is None
+
+
+def test_slab_arguments_rejected_before_any_device_call():
+    lib = B.load()
+    h = ctypes.c_void_p()
+    o = B.hermite_default_options()
+    assert lib.hermite_slab_create(16, 4, 3, 0.5, 1.0, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_create(1, 4, 3, 0.5, 1.0, None, ctypes.byref(h)) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_create(16, 0, 3, 0.5, 1.0, None, ctypes.byref(h)) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_create(1290, 1290, 3, 0.5, 1.0, None, ctypes.byref(h)) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_create(16, 4, 3, 1.5, 1.0, None, ctypes.byref(h)) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_create(16, 4, 2, 0.5, 1.0, None, ctypes.byref(h)) == B.HERMITE_EUNSUPPORTED
+    o.precision = B.HERMITE_PREC_FP32
+    assert lib.hermite_slab_create(16, 4, 3, 0.5, 1.0, ctypes.byref(o), ctypes.byref(h)) == B.HERMITE_EUNSUPPORTED
+    assert "FP64" in B.hermite_slab_last_error(None)
+    assert h.value is None
+
+
+def test_slab_null_calls_fail_cleanly():
+    lib = B.load()
+    assert lib.hermite_slab_set_initial(None, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_plane(None, 0, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_half_step(None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_gather(None, None, None, None) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_copy_plane(None, 0, None, 0) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_sync(None) == B.HERMITE_EINVAL
+    lib.hermite_slab_destroy(None)
