@@ -302,7 +302,7 @@ def advection_leg(B, torch, I, n: int = 150, steps: int = 200, warmup: int = 1) 
     return out
 
 
-def slab_leg(B, torch, I, n: int = 128, nz: int = 16, half_steps: int = 40) -> dict:
+def slab_leg(B, torch, I, n: int = 128, nz: int = 16, half_steps: int = 100, warmup: int = 20) -> dict:
     """One device's share of the headline grid cut into z-slabs (n x n x nz
     cells of the n^3 grid, m = 3, fused FP64 on the matrix cores): half steps
     of the slab kernel alone, and with the one-plane halo copy before each
@@ -335,7 +335,7 @@ def slab_leg(B, torch, I, n: int = 128, nz: int = 16, half_steps: int = 40) -> d
         res = {}
         for name, exchange, compute in (("kernel_only", False, True), ("with_plane_copy", True, True),
                                         ("plane_copy_only", True, False)):
-            run(2, exchange, compute)
+            run(warmup, exchange, compute)
             sl.sync()
             start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             start.record(stream)

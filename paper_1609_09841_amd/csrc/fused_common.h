@@ -126,21 +126,25 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
     }
 }
 
-// The same sweep over the rows (y, k) of a slab of nz cell planes: each XCD
-// owns nz/8 planes (a thin slab leaves some XCDs fewer), and the block of
-// rows its workgroups run together is at most as deep as its planes.
+// The same sweep over the rows (y, k) of a slab of nz cell planes. A deep
+// slab is split among the XCDs along z as the cube is; a thin one (fewer
+// than 4 planes per XCD) along y, so that each XCD still sweeps a block of
+// rows several planes deep and the second read of a node row hits its L2.
 template <class F>
 __device__ __forceinline__ void sweep_rows_slab(uint32_t n, uint32_t nz, int wave, int waves, F&& f) {
     const uint32_t wpx = gridDim.x / 8;
     const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
-    const uint32_t z0 = xcd * nz / 8, z1 = (xcd + 1) * nz / 8, pz = z1 - z0;
+    const bool by_z = nz >= 32;
+    const uint32_t z0 = by_z ? xcd * nz / 8 : 0, z1 = by_z ? (xcd + 1) * nz / 8 : nz;
+    const uint32_t y0 = by_z ? 0 : xcd * n / 8, y1 = by_z ? n : (xcd + 1) * n / 8;
+    const uint32_t pz = z1 - z0, py = y1 - y0;
     const uint32_t BZ = (wpx % 4 == 0 && pz >= 4) ? 4 : (wpx % 2 == 0 && pz >= 2) ? 2 : 1, BY = wpx / BZ;
     const uint32_t yy = w % BY, zz = w / BY;
-    const uint32_t nyb = (n + BY - 1) / BY, ngr = (pz + BZ - 1) / BZ;
+    const uint32_t nyb = (py + BY - 1) / BY, ngr = (pz + BZ - 1) / BZ;
     const uint32_t nbx = (n + 15) / 16;
     for (uint32_t it = 0; it < nyb * ngr; ++it) {
-        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
-        if (y >= n || z >= z1) continue;
+        const uint32_t y = y0 + (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+        if (y >= y1 || z >= z1) continue;
         for (uint32_t bx = wave; bx < nbx; bx += waves) f(bx * 16, y, z);
     }
 }
