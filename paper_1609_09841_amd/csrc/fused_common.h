@@ -104,12 +104,14 @@ __device__ __forceinline__ void butterfly8(const double* v, double* T) {
 // Persistent sweep: one workgroup per CU, gridDim.x a multiple of 8, and
 // workgroup b runs on XCD b % 8. Each XCD owns a slab of z-planes; its G/8
 // workgroups form a block of BY rows (y) x BZ planes (z) that sweeps the
-// slab, one x-row per workgroup per iteration, the waves of the workgroup
-// taking the row's 16-cell batches. A node row is read by the cells on both
-// sides of it in y and z; in this order those cells run at the same time on
-// the same XCD, so the second read hits L2 instead of coming back from memory
-// one iteration later. f(x0, y, z) runs the batch of cells x0 .. x0+15 of row
-// (y, z).
+// slab, one x-row segment per workgroup per iteration, the waves of the
+// workgroup taking its 16-cell batches (one each: a segment is 16 * waves
+// cells, and rows longer than that are swept one segment after the other,
+// so the block's working set does not grow with n). A node row is read by
+// the cells on both sides of it in y and z; in this order those cells run at
+// the same time on the same XCD, so the second read hits L2 instead of coming
+// back from memory one iteration later. f(x0, y, z) runs the batch of cells
+// x0 .. x0+15 of row (y, z).
 template <class F>
 __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& f) {
     const uint32_t wpx = gridDim.x / 8;  // workgroups per XCD
@@ -118,11 +120,14 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
     const uint32_t yy = w % BY, zz = w / BY;
     const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
     const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
-    const uint32_t nbx = (n + 15) / 16;
-    for (uint32_t it = 0; it < nyb * ngr; ++it) {
-        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
-        if (y >= n || z >= z1) continue;
-        for (uint32_t bx = wave; bx < nbx; bx += waves) f(bx * 16, y, z);
+    const uint32_t nbx = (n + 15) / 16, nseg = (nbx + waves - 1) / waves;
+    for (uint32_t sg = 0; sg < nseg; ++sg) {
+        const uint32_t bx = sg * waves + wave;
+        for (uint32_t it = 0; it < nyb * ngr; ++it) {
+            const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+            if (y >= n || z >= z1 || bx >= nbx) continue;
+            f(bx * 16, y, z);
+        }
     }
 }
 
@@ -141,31 +146,14 @@ __device__ __forceinline__ void sweep_rows_slab(uint32_t n, uint32_t nz, int wav
     const uint32_t BZ = (wpx % 4 == 0 && pz >= 4) ? 4 : (wpx % 2 == 0 && pz >= 2) ? 2 : 1, BY = wpx / BZ;
     const uint32_t yy = w % BY, zz = w / BY;
     const uint32_t nyb = (py + BY - 1) / BY, ngr = (pz + BZ - 1) / BZ;
-    const uint32_t nbx = (n + 15) / 16;
-    for (uint32_t it = 0; it < nyb * ngr; ++it) {
-        const uint32_t y = y0 + (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
-        if (y >= y1 || z >= z1) continue;
-        for (uint32_t bx = wave; bx < nbx; bx += waves) f(bx * 16, y, z);
-    }
-}
-
-// Same order for kernels whose workgroup computes a segment of up to `seg`
-// cells of one x-row together: f(x0, y, z) runs cells x0 .. x0+seg-1 of row
-// (y, z) (fewer at the end of the row) and is called by every thread of the
-// workgroup the same number of times (f may synchronise the workgroup).
-template <class F>
-__device__ __forceinline__ void sweep_segments(uint32_t n, uint32_t seg, F&& f) {
-    const uint32_t wpx = gridDim.x / 8;
-    const uint32_t BZ = (wpx % 4 == 0) ? 4 : (wpx % 2 == 0) ? 2 : 1, BY = wpx / BZ;
-    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
-    const uint32_t yy = w % BY, zz = w / BY;
-    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
-    const uint32_t nyb = (n + BY - 1) / BY, ngr = (z1 - z0 + BZ - 1) / BZ;
-    const uint32_t nsx = (n + seg - 1) / seg;
-    for (uint32_t it = 0; it < nyb * ngr; ++it) {
-        const uint32_t y = (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
-        if (y >= n || z >= z1) continue;
-        for (uint32_t sx = 0; sx < nsx; ++sx) f(sx * seg, y, z);
+    const uint32_t nbx = (n + 15) / 16, nseg = (nbx + waves - 1) / waves;
+    for (uint32_t sg = 0; sg < nseg; ++sg) {
+        const uint32_t bx = sg * waves + wave;
+        for (uint32_t it = 0; it < nyb * ngr; ++it) {
+            const uint32_t y = y0 + (it % nyb) * BY + yy, z = z0 + (it / nyb) * BZ + zz;
+            if (y >= y1 || z >= z1 || bx >= nbx) continue;
+            f(bx * 16, y, z);
+        }
     }
 }
 

@@ -174,3 +174,60 @@ def test_adjoint_errors():
         with pytest.raises(B.HermiteError) as e:
             s.adjoint_init()
         assert e.value.code == B.HERMITE_EUNSUPPORTED
+
+
+def test_differentiation_workload_small_copy():
+    """The differentiation workload's shape on a 16^3, m = 2 copy: Ricker
+    source at the cube centre, receivers on the node plane z = 0.75, misfit
+    against traces from perturbed initial data. Checks: the dot-product
+    identity of the whole sweep, and central differences of J for u0, u_t0
+    and the source series."""
+    n, m, steps = 16, 2, 10
+    M = m + 1
+    rng = np.random.default_rng(1609)
+    src = {"x": (0.5, 0.5, 0.5), "sigma": 2.0 / n, "freq": n / 8.0, "t0": 0.05, "amplitude": 20.0}
+    kz = int(round(0.75 * n))
+    rec = [(int(i), int(j), kz) for i, j in zip(rng.integers(0, n, 32), rng.integers(0, n, 32))]
+    u0 = _t(rng.standard_normal((M, M, M, n, n, n)))
+    ut0 = _t(rng.standard_normal((M, M, M, n, n, n)))
+    du = _t(rng.standard_normal((M, M, M, n, n, n)))
+    amps = _t(np.ones(2 * steps))
+    print(f"[differentiation copy] n={n} m={m} receivers on k={kz}", flush=True)
+    with B.Solver(n, m) as s:
+        s.set_receivers(rec)
+        s.set_source(src)
+        with torch.no_grad():
+            obs = receiver_traces(s, u0 + 0.1 * du, ut0, amps, steps)
+
+        def J(a, b, c):
+            return 0.5 * ((receiver_traces(s, a, b, c, steps) - obs) ** 2).sum()
+
+        x = [u0.clone().requires_grad_(), ut0.clone().requires_grad_(), amps.clone().requires_grad_()]
+        grads = torch.autograd.grad(J(*x), x)
+        for which in range(3):
+            d = [torch.zeros_like(v) for v in x]
+            d[which] = _t(rng.standard_normal(tuple(x[which].shape)))
+            eps = 1e-3
+            with torch.no_grad():
+                fd = (J(*[v + eps * dv for v, dv in zip(x, d)]).item()
+                      - J(*[v - eps * dv for v, dv in zip(x, d)]).item()) / (2 * eps)
+            ad = sum((g * dv).sum().item() for g, dv in zip(grads, d))
+            print(f"  direction {which}: fd {fd:.10e} adjoint {ad:.10e}", flush=True)
+            assert fd == pytest.approx(ad, rel=1e-7)
+        # dot-product identity of the sweep: <F x, y> = <x, F^T y>
+        y = [rng.standard_normal((M, M, M, n, n, n)) for _ in range(2)]
+        xs = [rng.standard_normal((M, M, M, n, n, n)) for _ in range(2)]
+    with B.Solver(n, m) as s:
+        s.set_initial(*xs)
+        s.step(steps)
+        fu, fut, _ = s.gather()
+        gu = torch.empty((M, M, M, n, n, n), dtype=torch.float64, device="cuda")
+        gut = torch.empty_like(gu)
+        s.adjoint_init(_t(y[0]), _t(y[1]))
+        s.adjoint_step(steps)
+        s.adjoint_gather(gu, gut)
+        s.sync()
+    lhs = np.sum(fu * y[0]) + np.sum(fut * y[1])
+    rhs = np.sum(xs[0] * gu.cpu().numpy()) + np.sum(xs[1] * gut.cpu().numpy())
+    scale = np.sqrt(np.sum(fu ** 2) + np.sum(fut ** 2)) * np.sqrt(np.sum(y[0] ** 2) + np.sum(y[1] ** 2))
+    assert abs(lhs - rhs) / scale <= 1e-13
