@@ -44,50 +44,88 @@ struct AxisOp {
     double k[M * 2 * M];  // K1[j][a], row-major
 };
 
+// The x1-lines of corner data, (a3, a2) = line L / P, L % P in the order
+// high derivative orders (small terms) first. Line L's 2M values come from
+// the 2 corners along x1 of its (s2, s3) and the M derivative orders d1.
+template <int M, int L>
+__device__ __forceinline__ void load_line(const double* __restrict__ src, size_t pitch, const Cell16& c, double* x) {
+    constexpr int P = 2 * M, a3i = L / P, a2i = L % P;
+    constexpr int s3 = a3i & 1, d3 = M - 1 - (a3i >> 1), s2 = a2i & 1, d2 = M - 1 - (a2i >> 1);
+#pragma unroll
+    for (int a1 = 0; a1 < P; ++a1) {
+        const int s1 = a1 / M, d1 = a1 % M;
+        x[a1] = src[(size_t)((d3 * M + d2) * M + d1) * pitch + c.corner[s1 + 2 * s2 + 4 * s3]];
+    }
+}
+
+// Lines requested ahead of the one being contracted (a ring of registers;
+// two at m = 3, where the accumulators leave room for no more without
+// spilling); the scheduling barrier after each line keeps the compiler from
+// pulling the loads back next to their use.
 template <int M>
-__global__ __launch_bounds__(kThreads, kMinWaves<M>) void advect_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                                          AxisOp<M> K, uint32_t n, size_t pitch, uint32_t off) {
+constexpr int kLineAhead = M == 4 ? 2 : 3;
+template <int M>
+constexpr int kLineRing = kLineAhead<M> + 1;
+
+template <int M, int L>
+struct LinePrologue {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t pitch, const Cell16& c,
+                                               double (*ring)[2 * M]) {
+        load_line<M, L>(src, pitch, c, ring[L]);
+        if constexpr (L + 1 < kLineAhead<M>) LinePrologue<M, L + 1>::run(src, pitch, c, ring);
+    }
+};
+
+template <int M, int L>
+struct Lines {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t pitch, const Cell16& c,
+                                               const AxisOp<M>& K, double* y, double* Y, double (*ring)[2 * M]) {
+        constexpr int P = 2 * M, a3i = L / P, a2i = L % P;
+        constexpr int a3 = (a3i & 1) * M + M - 1 - (a3i >> 1), a2 = (a2i & 1) * M + M - 1 - (a2i >> 1);
+        constexpr int A = kLineAhead<M>, R = kLineRing<M>;
+        if constexpr (L + A < P * P) load_line<M, L + A>(src, pitch, c, ring[(L + A) % R]);
+        const double* x = ring[L % R];
+        if constexpr (a2i == 0) {
+#pragma unroll
+            for (int t = 0; t < M * M; ++t) Y[t] = 0.0;
+        }
+#pragma unroll
+        for (int j1 = 0; j1 < M; ++j1) {
+            double z = 0.0;
+#pragma unroll
+            for (int d1 = M - 1; d1 >= 0; --d1) {
+                z = __builtin_fma(K.k[j1 * P + d1], x[d1], z);
+                z = __builtin_fma(K.k[j1 * P + M + d1], x[M + d1], z);
+            }
+#pragma unroll
+            for (int j2 = 0; j2 < M; ++j2) Y[j2 * M + j1] = __builtin_fma(K.k[j2 * P + a2], z, Y[j2 * M + j1]);
+        }
+        if constexpr (a2i == P - 1) {
+#pragma unroll
+            for (int j3 = 0; j3 < M; ++j3)
+#pragma unroll
+                for (int t = 0; t < M * M; ++t)
+                    y[j3 * M * M + t] = __builtin_fma(K.k[j3 * P + a3], Y[t], y[j3 * M * M + t]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (L + 1 < P * P) Lines<M, L + 1>::run(src, pitch, c, K, y, Y, ring);
+    }
+};
+
+template <int M>
+__global__ __launch_bounds__(kThreads, kMinWaves<M>) void advect_kernel(const double* __restrict__ src,
+                                                                        double* __restrict__ dst, AxisOp<M> K,
+                                                                        uint32_t n, size_t pitch, uint32_t off) {
     constexpr int P = 2 * M, M3 = M * M * M;
     const uint32_t node = blockIdx.x * kThreads + threadIdx.x;  // new node this lane writes
     if (node >= n * n * n) return;
     const Cell16 c = cell_writing(node, n, off);
-    double y[M3];
+    double y[M3], Y[M * M];
 #pragma unroll
     for (int t = 0; t < M3; ++t) y[t] = 0.0;
-    // high derivative orders (small terms) first
-#pragma unroll
-    for (int a3i = 0; a3i < P; ++a3i) {
-        const int s3 = a3i & 1, d3 = M - 1 - (a3i >> 1), a3 = s3 * M + d3;
-        double Y[M * M];
-#pragma unroll
-        for (int t = 0; t < M * M; ++t) Y[t] = 0.0;
-#pragma unroll
-        for (int a2i = 0; a2i < P; ++a2i) {
-            const int s2 = a2i & 1, d2 = M - 1 - (a2i >> 1), a2 = s2 * M + d2;
-            double x[P];
-#pragma unroll
-            for (int a1 = 0; a1 < P; ++a1) {
-                const int s1 = a1 / M, d1 = a1 % M;
-                x[a1] = src[(size_t)((d3 * M + d2) * M + d1) * pitch + c.corner[s1 + 2 * s2 + 4 * s3]];
-            }
-#pragma unroll
-            for (int j1 = 0; j1 < M; ++j1) {
-                double z = 0.0;
-#pragma unroll
-                for (int d1 = M - 1; d1 >= 0; --d1) {
-                    z = __builtin_fma(K.k[j1 * P + d1], x[d1], z);
-                    z = __builtin_fma(K.k[j1 * P + M + d1], x[M + d1], z);
-                }
-#pragma unroll
-                for (int j2 = 0; j2 < M; ++j2) Y[j2 * M + j1] = __builtin_fma(K.k[j2 * P + a2], z, Y[j2 * M + j1]);
-            }
-        }
-#pragma unroll
-        for (int j3 = 0; j3 < M; ++j3)
-#pragma unroll
-            for (int t = 0; t < M * M; ++t)
-                y[j3 * M * M + t] = __builtin_fma(K.k[j3 * P + a3], Y[t], y[j3 * M * M + t]);
-    }
+    double ring[kLineRing<M>][P];
+    LinePrologue<M, 0>::run(src, pitch, c, ring);
+    Lines<M, 0>::run(src, pitch, c, K, y, Y, ring);
 #pragma unroll
     for (int t = 0; t < M3; ++t) dst[(size_t)t * pitch + c.out] = y[t];
 }
