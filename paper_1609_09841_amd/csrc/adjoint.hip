@@ -13,12 +13,10 @@
 // node - s + off; the kernel gathers the 8 contributions at each node (no
 // scatter, no atomics, a fixed summation order).
 //
-// m = 1, 2 (adjoint_kernel): one lane per (node, input field fi), M^3
-// accumulators; the 8 cells are a runtime loop, classes, class rows and
-// columns are unrolled, so the operator entries are wave-uniform scalar
-// operands. m = 3 (adjoint_mfma_kernel below) butterflies the adjoint values
-// of the 8 neighbouring new nodes first and runs the transposed products on
-// the matrix cores, as many as the forward half step.
+// Both kernels gather at each node: they butterfly the adjoint values of the
+// 8 neighbouring new nodes first and then run the transposed class products,
+// as many as the forward half step (m = 3 on the matrix cores, m = 1, 2 on
+// the vector ALUs).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -55,47 +53,6 @@ struct AdjLayout {
         return (d1 & 1) | ((d2 & 1) << 1) | ((d3 & 1) << 2);
     }
 };
-
-template <int M>
-__global__ __launch_bounds__(kThreads) void adjoint_kernel(const double* __restrict__ lam_dst,
-                                                           double* __restrict__ lam_src,
-                                                           const double* __restrict__ K, uint32_t n, size_t pitch,
-                                                           uint32_t off) {
-    constexpr AdjLayout<M> L{};
-    constexpr int M3 = AdjLayout<M>::M3, RM = AdjLayout<M>::RM;
-    const uint32_t fi = blockIdx.x & 1;
-    const uint32_t node = (blockIdx.x >> 1) * kThreads + threadIdx.x;
-    if (node >= n * n * n) return;
-    const uint32_t i = node % n, t = node / n, j = t % n, k = t / n;
-    const double* __restrict__ Kf = K + (size_t)fi * M3;  // columns of input field fi
-    double acc[M3];
-#pragma unroll
-    for (int d = 0; d < M3; ++d) acc[d] = 0.0;
-    for (int s = 0; s < 8; ++s) {
-        const uint32_t s1 = s & 1, s2 = (s >> 1) & 1, s3 = s >> 2;
-        // new node of the cell with lower corner node - s: node - s + off
-        const uint32_t oi = (i + n - s1 + off) % n, oj = (j + n - s2 + off) % n, ok = (k + n - s3 + off) % n;
-        const size_t out = ((size_t)ok * n + oj) * n + oi;
-        double sg[8];
-#pragma unroll
-        for (int tt = 0; tt < 8; ++tt) sg[tt] = (__builtin_popcount((unsigned)tt & ~(unsigned)s & 7u) & 1) ? -1.0 : 1.0;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            double lp[RM];
-#pragma unroll
-            for (int r = 0; r < L.nrows[p]; ++r) lp[r] = lam_dst[(size_t)L.row_col[p][r] * pitch + out];
-#pragma unroll
-            for (int d = 0; d < M3; ++d) {
-                double h = 0.0;
-#pragma unroll
-                for (int r = 0; r < L.nrows[p]; ++r) h = __builtin_fma(Kf[((size_t)p * RM + r) * 2 * M3 + d], lp[r], h);
-                acc[d] = __builtin_fma(sg[p ^ AdjLayout<M>::par(d)], h, acc[d]);
-            }
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < M3; ++d) lam_src[(size_t)(fi * M3 + d) * pitch + node] = acc[d];
-}
 
 // traces[r] = u (d = 0) at receiver node nodes[r] of the primal grid.
 __global__ void record_kernel(const double* __restrict__ grid, const uint32_t* __restrict__ nodes, uint32_t nr,
@@ -246,6 +203,78 @@ __global__ __launch_bounds__(kMfWaves * 64) void adjoint_mfma_kernel(const doubl
     });
 }
 
+// ---------------------------------------------------------------------------
+// m = 1, 2 on the vector ALUs, the same gather form: one lane per node, all
+// 2 M^3 adjoint values. The 2 M^3 (class p, row r) columns of lam are
+// unrolled at compile time: the 8 neighbour values of column (p, r) are
+// butterflied once, and output c takes butterfly output p xor par(c) times
+// K_p[r][c], a wave-uniform scalar operand of the canonical operator.
+// Entries that vanish for every time step (even class parity along an axis,
+// row order 2 there, column order 0 there) are skipped.
+// ---------------------------------------------------------------------------
+template <int M>
+struct AdjSmall {
+    static constexpr int M3 = M * M * M, NC = 2 * M3;
+    int p[NC], r[NC];     // column step -> (class, class row)
+    bool zero[NC][NC];    // (column step, output c): structural zero
+    constexpr AdjSmall() : p(), r(), zero() {
+        constexpr AdjLayout<M> L{};
+        int k = 0;
+        for (int q = 0; q < 8; ++q)
+            for (int rr = 0; rr < L.nrows[q]; ++rr, ++k) {
+                p[k] = q;
+                r[k] = rr;
+                const int n1 = (M + 1 - (q & 1)) / 2, n2 = (M + 1 - ((q >> 1) & 1)) / 2;
+                const int nof = n1 * n2 * ((M + 1 - (q >> 2)) / 2), w = rr % nof;
+                const int o1 = w % n1, o2 = (w / n1) % n2, o3 = w / (n1 * n2);
+                for (int c = 0; c < NC; ++c) {
+                    const int d = c % M3, d1 = d % M, d2 = (d / M) % M, d3 = d / (M * M);
+                    zero[k][c] = ((q & 1) == 0 && o1 == 1 && d1 == 0) || (((q >> 1) & 1) == 0 && o2 == 1 && d2 == 0) ||
+                                 ((q >> 2) == 0 && o3 == 1 && d3 == 0);
+                }
+            }
+    }
+};
+
+template <int M, int S>
+struct AdjSmallSteps {
+    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t pitch, const fused::Cell16& nb,
+                                               const double* __restrict__ K, double* acc) {
+        constexpr AdjLayout<M> L{};
+        constexpr AdjSmall<M> A{};
+        constexpr int NC = AdjSmall<M>::NC, M3 = AdjSmall<M>::M3, RM = AdjLayout<M>::RM;
+        constexpr int p = A.p[S], r = A.r[S];
+        const double* __restrict__ b = lam + (size_t)L.row_col[p][r] * pitch;
+        double v[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = b[nb.corner[s]];
+        double U[8];
+        fused::butterfly8(v, U);
+        const double* __restrict__ kk = K + ((size_t)p * RM + r) * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (!A.zero[S][c]) acc[c] = __builtin_fma(kk[c], U[p ^ AdjLayout<M>::par(c % M3)], acc[c]);
+        if constexpr (S + 1 < NC) AdjSmallSteps<M, S + 1>::run(lam, pitch, nb, K, acc);
+    }
+};
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void adjoint_kernel(const double* __restrict__ lam_dst,
+                                                           double* __restrict__ lam_src,
+                                                           const double* __restrict__ K, uint32_t n, size_t pitch,
+                                                           uint32_t off) {
+    constexpr int NC = AdjSmall<M>::NC;
+    const uint32_t node = blockIdx.x * kThreads + threadIdx.x;
+    if (node >= n * n * n) return;
+    const fused::Cell16 nb = node_neighbours(node, n, off);
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    AdjSmallSteps<M, 0>::run(lam_dst, pitch, nb, K, acc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lam_src[(size_t)c * pitch + node] = acc[c];
+}
+
 }  // namespace
 
 size_t adjoint_mfma_operator_doubles() { return (size_t)kAdjOpDoubles; }
@@ -275,12 +304,11 @@ hipError_t launch_adjoint_mfma(const double* lam_dst, double* lam_src, const dou
 hipError_t launch_adjoint(int m, const double* lam_dst, double* lam_src, const double* K, int n, size_t pitch, int off,
                           hipStream_t st) {
     const uint32_t ncell = (uint32_t)n * n * n;
-    const dim3 grid(2 * ((ncell + kThreads - 1) / kThreads)), block(kThreads);
+    const dim3 grid((ncell + kThreads - 1) / kThreads), block(kThreads);
     switch (m) {
         case 1: hipLaunchKernelGGL(adjoint_kernel<2>, grid, block, 0, st, lam_dst, lam_src, K, (uint32_t)n, pitch, (uint32_t)off); break;
         case 2: hipLaunchKernelGGL(adjoint_kernel<3>, grid, block, 0, st, lam_dst, lam_src, K, (uint32_t)n, pitch, (uint32_t)off); break;
-        case 3: hipLaunchKernelGGL(adjoint_kernel<4>, grid, block, 0, st, lam_dst, lam_src, K, (uint32_t)n, pitch, (uint32_t)off); break;
-        default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;  // m = 3: launch_adjoint_mfma
     }
     return hipGetLastError();
 }

@@ -93,7 +93,7 @@ hipError_t launch_source(const SourceDesc* srcs, const uint32_t* prefix, uint32_
 hipError_t launch_source_dot(const SourceDesc* src, const uint32_t* prefix, uint32_t blocks, int m, int from,
                              long long host_steps, double* scal, double* partial, double* grad, hipStream_t st);
 
-// Transposed fused half step (FP64): lam_src (adjoint of the grid the half
+// Transposed fused half step (FP64, m = 1, 2): lam_src (adjoint of the grid the half
 // step reads) from lam_dst (adjoint of the grid it writes); K: canonical
 // class operators ([8][rows_max][2 M^3], fused_class_operators), device.
 hipError_t launch_adjoint(int m, const double* lam_dst, double* lam_src, const double* K, int n, size_t pitch, int off,
