@@ -61,6 +61,7 @@ extern "C" {
 #define HERMITE_KERNEL_AUTO 0  /* the matrix-core kernel */
 #define HERMITE_KERNEL_MFMA 1  /* FP64 matrix cores (v_mfma_f64_16x16x4) */
 #define HERMITE_KERNEL_VALU 2  /* FP64 vector FMAs, operator entries as scalar operands */
+#define HERMITE_KERNEL_MFMA4 3 /* FP64 matrix cores in 4x4 tiles (v_mfma_f64_4x4x4, 4 blocks) */
 
 /* Equation (Sec. 2). WAVE: u_tt = c^2 Lap u as the first-order system
  * (u, u_t), two fields per node. ADVECTION: u_t = c (u_x1 + u_x2 + u_x3),

@@ -29,6 +29,7 @@ HERMITE_EVOLVE_RK4 = 1
 HERMITE_KERNEL_AUTO = 0
 HERMITE_KERNEL_MFMA = 1
 HERMITE_KERNEL_VALU = 2
+HERMITE_KERNEL_MFMA4 = 3
 HERMITE_EQ_WAVE = 0
 HERMITE_EQ_ADVECTION = 1
 HERMITE_SLAB_PRIMAL_FIRST = 0
@@ -36,7 +37,8 @@ HERMITE_SLAB_PRIMAL_HALO = 1
 HERMITE_SLAB_DUAL_LAST = 2
 HERMITE_SLAB_DUAL_HALO = 3
 EQUATIONS = {"wave": HERMITE_EQ_WAVE, "advection": HERMITE_EQ_ADVECTION}
-KERNELS = {"auto": HERMITE_KERNEL_AUTO, "mfma": HERMITE_KERNEL_MFMA, "valu": HERMITE_KERNEL_VALU}
+KERNELS = {"auto": HERMITE_KERNEL_AUTO, "mfma": HERMITE_KERNEL_MFMA, "valu": HERMITE_KERNEL_VALU,
+           "mfma4": HERMITE_KERNEL_MFMA4}
 
 PRECISIONS = {"fp64": HERMITE_PREC_FP64, "fp32": HERMITE_PREC_FP32, "bf16x3": HERMITE_PREC_BF16X3}
 EVOLUTIONS = {"taylor": HERMITE_EVOLVE_TAYLOR, "rk4": HERMITE_EVOLVE_RK4}

@@ -30,7 +30,7 @@ struct hermite_ctx {
     bool own_stream = false;
     int device = 0;
     int cus = 0;             // compute units of the device (persistent grids)
-    int m3_kernel = 0;       // m = 3 fused FP64: 0 vector ALUs, 1 matrix cores
+    int m3_kernel = 0;       // m = 3 fused FP64: 0 vector ALUs, 1 matrix cores (16x16), 2 matrix cores (4x4 tiles)
     int precision = 0;       // HERMITE_PREC_*: contraction arithmetic
     int nf = 2;              // fields per node: 2 (wave: u, u_t) or 1 (advection)
     std::vector<double> K1;  // advection: per-axis operator (M x 2M)
@@ -135,6 +135,8 @@ int half_step(hermite_ctx* ctx, int from) {
                                             ctx->stream);
         } else if (ctx->m == 3 && ctx->m3_kernel == 1) {
             e = hermite::launch_fused_mfma(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
+        } else if (ctx->m == 3 && ctx->m3_kernel == 2) {
+            e = hermite::launch_fused_mfma4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
         } else if (ctx->m == 3) {
             e = hermite::launch_fused_valu4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         } else {
@@ -191,7 +193,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     if (o.q < 0 || o.q > 64) return fail(nullptr, HERMITE_EINVAL, "q=%d outside [0, 64]", o.q);
     if (o.fused != 0 && o.fused != 1) return fail(nullptr, HERMITE_EINVAL, "fused=%d", o.fused);
     if (o.poison != 0 && o.poison != 1) return fail(nullptr, HERMITE_EINVAL, "poison=%d", o.poison);
-    if (o.kernel < HERMITE_KERNEL_AUTO || o.kernel > HERMITE_KERNEL_VALU)
+    if (o.kernel < HERMITE_KERNEL_AUTO || o.kernel > HERMITE_KERNEL_MFMA4)
         return fail(nullptr, HERMITE_EINVAL, "kernel=%d", o.kernel);
     if (o.equation != HERMITE_EQ_WAVE && o.equation != HERMITE_EQ_ADVECTION)
         return fail(nullptr, HERMITE_EINVAL, "equation=%d", o.equation);
@@ -267,7 +269,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipDeviceGetAttribute"));
     ctx->precision = o.precision;
-    ctx->m3_kernel = (o.kernel == HERMITE_KERNEL_VALU) ? 0 : 1;
+    ctx->m3_kernel = (o.kernel == HERMITE_KERNEL_VALU) ? 0 : (o.kernel == HERMITE_KERNEL_MFMA4) ? 2 : 1;
     std::vector<unsigned char> Kdev;
     if (nf == 1) {
         ctx->K1 = hermite::advection_axis_operator(m, ctx->lam);
@@ -278,6 +280,9 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     } else if (m == 3 && o.fused && ctx->m3_kernel == 1) {
         Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
         hermite::mfma_permute_operators(K.data(), (double*)Kdev.data());
+    } else if (m == 3 && o.fused && ctx->m3_kernel == 2) {
+        Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
+        hermite::mfma4_arrange_operators(K.data(), (double*)Kdev.data());
     } else if (m == 3) {
         Kdev.resize(hermite::valu4_operator_doubles() * sizeof(double));
         hermite::valu4_build_operators(K.data(), (double*)Kdev.data());

@@ -87,6 +87,52 @@ struct Steps {
     }
 };
 
+// The same K-step in 4x4 tiles on v_mfma_f64_4x4x4f64 (4 blocks), which runs
+// at 1.55x the FP64 rate of the 16x16x4 instruction on gfx950. Block b (lane
+// bits 2-3) multiplies A[i][k] (lane 16k + 4b + i) by B[k][j] (lane 16k + 4b +
+// j) into D[i][j] (lane 16i + 4b + j). With block b taking cells 4b .. 4b+3,
+// B is exactly the 16x16 kernel's operand (lane 16q + cell: the butterfly
+// output of column q for that cell), and D row i lands in quarter i at the
+// cell's lane. Per class, 4 instructions cover the 16 rows as row tiles ri
+// whose row i is class row 4i + ri, so quarter q accumulates class rows
+// 4q + ri, ri = 0..3: the 16x16 kernel's accumulator layout. The tile's 16
+// operator values are the same in all blocks; every block reads them from LDS.
+template <int T>
+struct Steps4 {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& c,
+                                               const uint32_t* packed, int lane, const double* sK,
+                                               double (*acc)[4], double (*ring)[8]) {
+        constexpr MfmaSchedule S{};
+        constexpr int dp = S.dpar[T];
+        if constexpr (T + kAhead < 32) load_step<T + kAhead>(src, plane, c, packed, ring[(T + kAhead) % kRing]);
+        double Tv[8];
+        butterfly8(ring[T % kRing], Tv);
+        // this lane's A[i][k] (k = lane / 16, i = lane % 4) for row tiles
+        // 2 rp and 2 rp + 1 of class p: one 16-byte read; a step's 32 tiles
+        // are 4 KB, so every read of the step has an immediate offset
+        const int at = ((lane >> 4) << 2) | (lane & 3);
+        const double2* __restrict__ sT = reinterpret_cast<const double2*>(sK) + (size_t)T * 8 * 2 * 16 + at;
+        double2 a[2][2];  // [class parity of the pipeline][rp]
+#pragma unroll
+        for (int rp = 0; rp < 2; ++rp) a[0][rp] = sT[(0 * 2 + rp) * 16];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            if (p + 1 < 8) {
+#pragma unroll
+                for (int rp = 0; rp < 2; ++rp) a[(p + 1) & 1][rp] = sT[((p + 1) * 2 + rp) * 16];
+            }
+#pragma unroll
+            for (int ri = 0; ri < 4; ++ri) {
+                const double2 av = a[p & 1][ri >> 1];
+                acc[p][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64((ri & 1) ? av.y : av.x, Tv[p ^ dp], acc[p][ri], 0,
+                                                                0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (T + 1 < 32) Steps4<T + 1>::run(src, plane, c, packed, lane, sK, acc, ring);
+    }
+};
+
 // The first kAhead steps' corner values, before the step chain starts.
 template <int T>
 struct Prologue {
@@ -114,7 +160,7 @@ __constant__ ColTable kColTable = ColTable();
 // the row compute a copy of the last cell and store nothing.
 // SLAB: z is a buffer plane of a slab (fused::slab_cell_nodes) instead of a
 // plane of the periodic cube.
-template <bool SLAB = false>
+template <bool SLAB = false, bool TILE4 = false>
 __device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t plane,
                                           uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
                                           int cl, int q, uint32_t* packed, const double* sK) {
@@ -138,7 +184,18 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     for (int p = 0; p < 8; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
     double ring[kRing][8];
     Prologue<0>::run(src, plane, c, packed, ring);
-    Steps<0>::run(src, plane, c, packed, lane, sK, acc, ring);
+    if constexpr (TILE4) {
+        double acc4[8][4];
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc4[p][r] = 0.0;
+        Steps4<0>::run(src, plane, c, packed, lane, sK, acc4, ring);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) acc[p] = d4{acc4[p][0], acc4[p][1], acc4[p][2], acc4[p][3]};
+    } else {
+        Steps<0>::run(src, plane, c, packed, lane, sK, acc, ring);
+    }
     if (!valid) return;
     // logical output row 4q + r of class p (register r of quarter q): field q/2,
     // derivative orders j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2
@@ -170,6 +227,25 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* _
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
     fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
         run_batch(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
+    });
+}
+
+// The periodic cube on the 4x4-tile instruction (Steps4); operators from
+// mfma4_arrange_operators.
+__global__ __launch_bounds__(kWaves * 64) void fused_mfma4_kernel(const double* __restrict__ src,
+                                                                  double* __restrict__ dst,
+                                                                  const double* __restrict__ K4, uint32_t n,
+                                                                  size_t pitch, uint32_t off) {
+    __shared__ double sK[kOpDoubles];
+    for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = K4[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    uint32_t packed[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
+    fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
+        run_batch<false, true>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
     });
 }
 
@@ -251,6 +327,29 @@ hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* 
     if (grid < 8 || grid % 8 != 0 || nz < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fused_mfma_slab_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Kperm, (uint32_t)n,
                        (uint32_t)nz, pitch, (uint32_t)off);
+    return hipGetLastError();
+}
+
+void mfma4_arrange_operators(const double* K, double* K4) {
+    // K: [8][16][128] canonical class operators. Tile ri = 2 rp + h of class p
+    // at step t: A[i][k] = K[p][4 i + ri][col(t, k)], stored at
+    // ((((t 8 + p) 2 + rp) 16 + 4 k + i) 2 + h: a lane reads its two tiles of
+    // a row-tile pair as one 16-byte value.
+    constexpr MfmaSchedule S{};
+    for (int t = 0; t < 32; ++t)
+        for (int p = 0; p < 8; ++p)
+            for (int ri = 0; ri < 4; ++ri)
+                for (int k = 0; k < 4; ++k)
+                    for (int i = 0; i < 4; ++i)
+                        K4[((((size_t)t * 8 + p) * 2 + (ri >> 1)) * 16 + 4 * k + i) * 2 + (ri & 1)] =
+                            K[((size_t)p * 16 + 4 * i + ri) * 128 + S.col[t][k]];
+}
+
+hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
+                              hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fused_mfma4_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, K4, (uint32_t)n, pitch,
+                       (uint32_t)off);
     return hipGetLastError();
 }
 

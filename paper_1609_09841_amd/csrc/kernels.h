@@ -27,6 +27,11 @@ hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm
                              int grid, hipStream_t st);
 void mfma_permute_operators(const double* K, double* Kperm);
 size_t mfma_operator_doubles();
+// The same half step in 4x4 tiles (v_mfma_f64_4x4x4f64); K4 from
+// mfma4_arrange_operators (mfma_operator_doubles() doubles).
+hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
+                              hipStream_t st);
+void mfma4_arrange_operators(const double* K, double* K4);
 // One z-slab of nz cell planes of a periodic n x n x (shards * nz) grid:
 // src and dst hold nz + 1 node planes of n^2 nodes per column (the slab
 // layout of fused::slab_cell_nodes); off as launch_fused_mfma.

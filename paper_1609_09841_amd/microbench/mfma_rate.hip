@@ -90,6 +90,18 @@ __global__ __launch_bounds__(256) void k(double* out, int iters) {
         float s = 0;
         for (int p = 0; p < 8; ++p) s += acc[p][0] + acc[p][1] + acc[p][2] + acc[p][3];
         out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+    } else if constexpr (KIND == 6) {
+        // FP64 matrix cores in 4x4 tiles: v_mfma_f64_4x4x4f64, 4 blocks per instruction
+        double acc[8];
+        for (int p = 0; p < 8; ++p) acc[p] = 0.0;
+        double a = 1.0 + lane * 1e-3, b = 0.5 - lane * 1e-3;
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int p = 0; p < 8; ++p) acc[p] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[p], 0, 0, 0);
+        }
+        double s = 0;
+        for (int p = 0; p < 8; ++p) s += acc[p];
+        out[blockIdx.x * blockDim.x + threadIdx.x] = s;
     } else {
         // FP64 VALU FMA chains for comparison
         double acc[16];
@@ -196,6 +208,7 @@ int main() {
     // or their sum (shared units). Reported TFLOP/s counts both kinds.
     run<4>("mixed f64 mfma+valu waves", 0.5 * (2.0 * 16 * 16 * 4 * 8) + 0.5 * (2.0 * 64 * 128), 1);
     run<5>("mfma_f32_16x16x32_bf16", 2.0 * 16 * 16 * 32, 8);
+    run<6>("mfma_f64_4x4x4 (4 blocks)", 2.0 * 4 * 4 * 4 * 4, 8);
     run_scalar_operand(2);     // 1 KB: always in the scalar cache
     run_scalar_operand(128);   // 64 KB streamed per wave
     return 0;

@@ -62,7 +62,7 @@ def test_create_rejects_bad_arguments(args, what):
 
 @pytest.mark.parametrize("field,value", [
     ("precision", 3), ("precision", -1), ("evolution", 2), ("rk_substeps", -1), ("rk_substeps", 65),
-    ("q", -1), ("q", 65), ("fused", 2), ("poison", 5), ("kernel", -1), ("kernel", 3),
+    ("q", -1), ("q", 65), ("fused", 2), ("poison", 5), ("kernel", -1), ("kernel", 4),
 ])
 def test_create_rejects_bad_options(field, value):
     o = B.hermite_default_options()

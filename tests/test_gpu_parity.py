@@ -290,3 +290,24 @@ def test_m3_vector_kernel_against_oracle_and_matrix_kernel(n, evolution):
         assert rel(g_u, ou) <= max(TOL, 3 * fu) and rel(g_v, ov) <= max(TOL, 3 * fv)
         assert rel(g_u, lu) <= max(TOL, 1.5 * fu) and rel(g_v, lv) <= max(TOL, 1.5 * fv)
     assert rel(vu, mu) <= max(TOL, 3 * fu) and rel(vv, mv) <= max(TOL, 3 * fv)
+
+
+@pytest.mark.parametrize("evolution", ["taylor", "rk4"])
+@pytest.mark.parametrize("n", [3, 7, 16, 21])
+def test_m3_tile4_kernel_against_oracle_and_matrix_kernel(n, evolution):
+    """The m = 3 fused half step in 4x4 tiles (kernel="mfma4",
+    v_mfma_f64_4x4x4) runs the same column schedule as the 16x16 kernel:
+    both must meet the oracle bound and agree with each other."""
+    u0, ut0 = I.fourier_exact(n, 3, I.fourier_modes(kmax=1), t=0.05)
+    u0, ut0 = u0.numpy(), ut0.numpy()
+    steps = 3
+    tu, tv, _ = gpu_run(n, 3, u0, ut0, steps, fused=True, evolution=evolution, kernel="mfma4")
+    mu, mv, _ = gpu_run(n, 3, u0, ut0, steps, fused=True, evolution=evolution, kernel="mfma")
+    ou, ov = O.run(n, 3, 0.5, 1.0, u0, ut0, steps, evolution)
+    lu, lv = O.run(n, 3, 0.5, 1.0, u0, ut0, steps, evolution, ld=True)
+    fu, fv = rel(ou, lu), rel(ov, lv)
+    print(f"  mfma4-oracle u {rel(tu, ou):.2e} ut {rel(tv, ov):.2e}; mfma4-mfma u {rel(tu, mu):.2e} "
+          f"ut {rel(tv, mv):.2e}; oracle floor u {fu:.2e} ut {fv:.2e}", flush=True)
+    assert rel(tu, ou) <= max(TOL, 3 * fu) and rel(tv, ov) <= max(TOL, 3 * fv)
+    assert rel(tu, lu) <= max(TOL, 1.5 * fu) and rel(tv, lv) <= max(TOL, 1.5 * fv)
+    assert rel(tu, mu) <= max(TOL, 3 * fu) and rel(tv, mv) <= max(TOL, 3 * fv)
