@@ -360,18 +360,32 @@ int hermite_slab_plane(hermite_slab *s, int which, void **dev, size_t *pitch_byt
  * has taken an even number of half steps, dual -> primal otherwise. The
  * halo plane it reads must be filled (stream-ordered) before the call.
  * Returns in *next_halo (if not NULL) the HERMITE_SLAB_*_HALO plane the
- * following half step reads. */
+ * following half step reads. Same as hermite_slab_half_step_part with
+ * HERMITE_SLAB_ALL. */
 int hermite_slab_half_step(hermite_slab *s, int *next_halo);
+/* One half step in two parts, so that the halo's exchange can overlap the
+ * cells that do not read it: HERMITE_SLAB_INTERIOR enqueues every cell plane
+ * but the one that reads the halo (the top one in a primal -> dual half
+ * step, the bottom one after), and needs no halo; *next_halo then names the
+ * halo this half step's HERMITE_SLAB_BOUNDARY call reads, which enqueues that
+ * plane and completes the half step. The interior part neither reads nor
+ * writes the halo plane or the plane the neighbour copies.
+ * HERMITE_SLAB_ALL = both at once. HERMITE_ESTATE for a part out of order. */
+#define HERMITE_SLAB_INTERIOR 1
+#define HERMITE_SLAB_BOUNDARY 2
+#define HERMITE_SLAB_ALL 3
+int hermite_slab_half_step_part(hermite_slab *s, int part, int *next_halo);
 /* After an even number of half steps: the slab's own planes (layout as
  * set_initial; either pointer may be NULL) and t = full steps * dt;
  * synchronous. HERMITE_ESTATE after an odd number. */
 int hermite_slab_gather(hermite_slab *s, double *u, double *ut, double *t_out);
 /* Copy plane `src_which` of slab `src` into plane `dst_which` of `dst`
  * (e.g. PRIMAL_FIRST of the slab above into PRIMAL_HALO of this one), as
- * one 2-D copy enqueued on dst's stream; the slabs may sit on different
- * devices (a peer copy). The plane of src must be complete when the copy
- * runs: same stream, or src synchronised. */
-int hermite_slab_copy_plane(hermite_slab *dst, int dst_which, hermite_slab *src, int src_which);
+ * one 2-D copy enqueued on `stream` (a hipStream_t; NULL = dst's stream);
+ * the slabs may sit on different devices (a peer copy). The plane of src
+ * must be complete when the copy runs, and dst must not read the plane
+ * until it has: same stream, or events between the streams. */
+int hermite_slab_copy_plane(hermite_slab *dst, int dst_which, hermite_slab *src, int src_which, void *stream);
 int hermite_slab_sync(hermite_slab *s);
 void hermite_slab_destroy(hermite_slab *s);
 const char *hermite_slab_last_error(const hermite_slab *s);

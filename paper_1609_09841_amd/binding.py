@@ -36,6 +36,9 @@ HERMITE_SLAB_PRIMAL_FIRST = 0
 HERMITE_SLAB_PRIMAL_HALO = 1
 HERMITE_SLAB_DUAL_LAST = 2
 HERMITE_SLAB_DUAL_HALO = 3
+HERMITE_SLAB_INTERIOR = 1
+HERMITE_SLAB_BOUNDARY = 2
+HERMITE_SLAB_ALL = 3
 EQUATIONS = {"wave": HERMITE_EQ_WAVE, "advection": HERMITE_EQ_ADVECTION}
 KERNELS = {"auto": HERMITE_KERNEL_AUTO, "mfma": HERMITE_KERNEL_MFMA, "valu": HERMITE_KERNEL_VALU,
            "mfma4": HERMITE_KERNEL_MFMA4}
@@ -53,6 +56,7 @@ EXPORTS = (
     "hermite_batch_last_error", "hermite_set_receivers", "hermite_set_source_series", "hermite_step_record",
     "hermite_adjoint_init", "hermite_adjoint_step", "hermite_adjoint_gather", "hermite_state_finite",
     "hermite_slab_create", "hermite_slab_set_initial", "hermite_slab_plane", "hermite_slab_half_step",
+    "hermite_slab_half_step_part",
     "hermite_slab_gather", "hermite_slab_copy_plane", "hermite_slab_sync", "hermite_slab_destroy",
     "hermite_slab_last_error",
 )
@@ -189,9 +193,11 @@ def load(path: str = LIB_PATH):
     lib.hermite_slab_plane.restype = ip
     lib.hermite_slab_half_step.argtypes = [vp, ctypes.POINTER(ip)]
     lib.hermite_slab_half_step.restype = ip
+    lib.hermite_slab_half_step_part.argtypes = [vp, ip, ctypes.POINTER(ip)]
+    lib.hermite_slab_half_step_part.restype = ip
     lib.hermite_slab_gather.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_double)]
     lib.hermite_slab_gather.restype = ip
-    lib.hermite_slab_copy_plane.argtypes = [vp, ip, vp, ip]
+    lib.hermite_slab_copy_plane.argtypes = [vp, ip, vp, ip, vp]
     lib.hermite_slab_copy_plane.restype = ip
     lib.hermite_slab_sync.argtypes = [vp]
     lib.hermite_slab_sync.restype = ip
@@ -574,10 +580,19 @@ class Slab:
         _scheck(self._lib.hermite_slab_gather(self._s, _dptr(u), _dptr(ut), ctypes.byref(t)), self._s)
         return u, ut, t.value
 
-    def copy_plane_from(self, which: int, src: "Slab", src_which: int):
+    def half_step_part(self, part: int) -> int:
+        """hermite_slab_half_step_part: HERMITE_SLAB_INTERIOR, _BOUNDARY or _ALL;
+        returns the halo plane that the next part or half step reads."""
+        nxt = ctypes.c_int()
+        _scheck(self._lib.hermite_slab_half_step_part(self._s, int(part), ctypes.byref(nxt)), self._s)
+        return nxt.value
+
+    def copy_plane_from(self, which: int, src: "Slab", src_which: int, stream=None):
         """Fill plane `which` of this slab from plane `src_which` of `src`
-        (hermite_slab_copy_plane: ordered on this slab's stream)."""
-        _scheck(self._lib.hermite_slab_copy_plane(self._s, int(which), src._s, int(src_which)), self._s)
+        (hermite_slab_copy_plane), on `stream` (a torch stream or handle;
+        None: this slab's stream)."""
+        st = None if stream is None else ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        _scheck(self._lib.hermite_slab_copy_plane(self._s, int(which), src._s, int(src_which), st), self._s)
 
     def sync(self):
         _scheck(self._lib.hermite_slab_sync(self._s), self._s)

@@ -131,16 +131,18 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
     }
 }
 
-// The same sweep over the rows (y, k) of a slab of nz cell planes. A deep
-// slab is split among the XCDs along z as the cube is; a thin one (fewer
-// than 4 planes per XCD) along y, so that each XCD still sweeps a block of
-// rows several planes deep and the second read of a node row hits its L2.
+// The same sweep over the rows (y, k) of the cell planes k0 .. k1-1 of a
+// slab. A deep range is split among the XCDs along z as the cube is; a thin
+// one (fewer than 4 planes per XCD) along y, so that each XCD still sweeps a
+// block of rows several planes deep and the second read of a node row hits
+// its L2.
 template <class F>
-__device__ __forceinline__ void sweep_rows_slab(uint32_t n, uint32_t nz, int wave, int waves, F&& f) {
+__device__ __forceinline__ void sweep_rows_slab(uint32_t n, uint32_t k0, uint32_t k1, int wave, int waves, F&& f) {
     const uint32_t wpx = gridDim.x / 8;
     const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t nz = k1 - k0;
     const bool by_z = nz >= 32;
-    const uint32_t z0 = by_z ? xcd * nz / 8 : 0, z1 = by_z ? (xcd + 1) * nz / 8 : nz;
+    const uint32_t z0 = k0 + (by_z ? xcd * nz / 8 : 0), z1 = k0 + (by_z ? (xcd + 1) * nz / 8 : nz);
     const uint32_t y0 = by_z ? 0 : xcd * n / 8, y1 = by_z ? n : (xcd + 1) * n / 8;
     const uint32_t pz = z1 - z0, py = y1 - y0;
     const uint32_t BZ = (wpx % 4 == 0 && pz >= 4) ? 4 : (wpx % 2 == 0 && pz >= 2) ? 2 : 1, BY = wpx / BZ;

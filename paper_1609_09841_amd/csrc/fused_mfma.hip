@@ -250,11 +250,12 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma4_kernel(const double* 
 }
 
 // One z-slab of a periodic grid sharded over GPUs: the cells on buffer planes
-// 0 .. nz-1 (fused::slab_cell_nodes), the same per-cell arithmetic.
+// k0 .. k1-1 (fused::slab_cell_nodes), the same per-cell arithmetic.
 __global__ __launch_bounds__(kWaves * 64) void fused_mfma_slab_kernel(const double* __restrict__ src,
                                                                       double* __restrict__ dst,
                                                                       const double* __restrict__ Kperm, uint32_t n,
-                                                                      uint32_t nz, size_t pitch, uint32_t off) {
+                                                                      uint32_t k0, uint32_t k1, size_t pitch,
+                                                                      uint32_t off) {
     __shared__ double sK[kOpDoubles];
     for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = Kperm[i];
     __syncthreads();
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_slab_kernel(const doub
     uint32_t packed[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
-    fused::sweep_rows_slab(n, nz, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
+    fused::sweep_rows_slab(n, k0, k1, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
         run_batch<true>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
     });
 }
@@ -322,11 +323,12 @@ void mfma_permute_operators(const double* K, double* Kperm) {
             }
 }
 
-hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* Kperm, int n, int nz, size_t pitch,
-                                  int off, int grid, hipStream_t st) {
-    if (grid < 8 || grid % 8 != 0 || nz < 1) return hipErrorInvalidValue;
+hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* Kperm, int n, int k0, int k1,
+                                  size_t pitch, int off, int grid, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0 || k0 < 0 || k1 < k0) return hipErrorInvalidValue;
+    if (k1 == k0) return hipSuccess;
     hipLaunchKernelGGL(fused_mfma_slab_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Kperm, (uint32_t)n,
-                       (uint32_t)nz, pitch, (uint32_t)off);
+                       (uint32_t)k0, (uint32_t)k1, pitch, (uint32_t)off);
     return hipGetLastError();
 }
 

@@ -32,11 +32,12 @@ size_t mfma_operator_doubles();
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
                               hipStream_t st);
 void mfma4_arrange_operators(const double* K, double* K4);
-// One z-slab of nz cell planes of a periodic n x n x (shards * nz) grid:
-// src and dst hold nz + 1 node planes of n^2 nodes per column (the slab
-// layout of fused::slab_cell_nodes); off as launch_fused_mfma.
-hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* Kperm, int n, int nz, size_t pitch,
-                                  int off, int grid, hipStream_t st);
+// Cell planes k0 .. k1-1 (no launch if empty) of one z-slab of nz cell
+// planes of a periodic n x n x (shards * nz) grid: src and dst hold nz + 1
+// node planes of n^2 nodes per column (the slab layout of
+// fused::slab_cell_nodes); off as launch_fused_mfma.
+hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* Kperm, int n, int k0, int k1,
+                                  size_t pitch, int off, int grid, hipStream_t st);
 
 // Same fused FP64 half step for m = 3 on the vector ALUs: one lane per cell
 // and output field, operator entries as scalar operands. Kv:

@@ -1,7 +1,9 @@
 // One z-slab of a periodic grid sharded over devices (hermite_slab_*): the
 // fused m = 3 FP64 half step (Sec. 3.3) on the matrix cores, over the slab's
 // own cell planes, with the one plane each half step reads from a neighbour
-// held as a halo plane that the caller fills.
+// held as a halo plane that the caller fills. A half step can run in two
+// parts: the cells that do not read the halo (all but one cell plane), which
+// may overlap the halo's exchange, then the one plane that does.
 //
 // Buffers: each grid holds nz + 1 node planes per column (column pitch as the
 // cube's grids). Primal: planes 0 .. nz-1 = own planes z0 .. z0+nz-1, plane nz
@@ -37,6 +39,7 @@ struct hermite_slab {
     void* K = nullptr;                     // class operators, matrix-core layout
     bool has_state = false;
     long long half_steps = 0;
+    bool interior_done = false;            // the current half step's interior cells are enqueued
     std::string err;
 };
 
@@ -182,6 +185,7 @@ int hermite_slab_set_initial(hermite_slab* s, const double* u, const double* ut)
     SCHECK(s, hipStreamSynchronize(s->stream), "set_initial");
     s->has_state = true;
     s->half_steps = 0;
+    s->interior_done = false;
     return HERMITE_OK;
 }
 
@@ -201,26 +205,56 @@ int hermite_slab_plane(hermite_slab* s, int which, void** dev, size_t* pitch_byt
     return HERMITE_OK;
 }
 
-int hermite_slab_half_step(hermite_slab* s, int* next_halo) {
+int hermite_slab_half_step_part(hermite_slab* s, int part, int* next_halo) {
     if (!s) return sfail(nullptr, HERMITE_EINVAL, "slab is NULL");
-    if (!s->has_state) return sfail(s, HERMITE_ESTATE, "hermite_slab_half_step before hermite_slab_set_initial");
+    if (part != HERMITE_SLAB_INTERIOR && part != HERMITE_SLAB_BOUNDARY && part != HERMITE_SLAB_ALL)
+        return sfail(s, HERMITE_EINVAL, "part=%d is not HERMITE_SLAB_INTERIOR, _BOUNDARY or _ALL", part);
+    if (!s->has_state) return sfail(s, HERMITE_ESTATE, "slab half step before hermite_slab_set_initial");
+    if (part == HERMITE_SLAB_BOUNDARY && !s->interior_done)
+        return sfail(s, HERMITE_ESTATE, "HERMITE_SLAB_BOUNDARY before the half step's HERMITE_SLAB_INTERIOR");
+    if (part != HERMITE_SLAB_BOUNDARY && s->interior_done)
+        return sfail(s, HERMITE_ESTATE, "the half step's interior is enqueued: HERMITE_SLAB_BOUNDARY comes next");
     int rc = slab_device(s);
     if (rc) return rc;
     const int from = (int)(s->half_steps & 1);  // 0: primal -> dual
+    // the one cell plane that reads the halo: the top one (primal halo above)
+    // in the primal -> dual half step, the bottom one (dual halo below) after
+    const int kb = from ? 0 : s->nz - 1;
+    int k0 = 0, k1 = s->nz;
+    if (part == HERMITE_SLAB_INTERIOR) {
+        k0 = from ? 1 : 0;
+        k1 = from ? s->nz : s->nz - 1;
+    } else if (part == HERMITE_SLAB_BOUNDARY) {
+        k0 = kb;
+        k1 = kb + 1;
+    }
     SCHECK(s,
-           hermite::launch_fused_mfma_slab(s->grid[from], s->grid[1 - from], (const double*)s->K, s->n, s->nz,
+           hermite::launch_fused_mfma_slab(s->grid[from], s->grid[1 - from], (const double*)s->K, s->n, k0, k1,
                                            s->pitch, from, s->grid_blocks, s->stream),
            "slab half-step launch");
-    ++s->half_steps;
-    if (next_halo) *next_halo = (s->half_steps & 1) ? HERMITE_SLAB_DUAL_HALO : HERMITE_SLAB_PRIMAL_HALO;
+    if (part == HERMITE_SLAB_INTERIOR) {
+        s->interior_done = true;
+    } else {
+        s->interior_done = false;
+        ++s->half_steps;
+    }
+    if (next_halo)
+        *next_halo = (part == HERMITE_SLAB_INTERIOR) ? (from ? HERMITE_SLAB_DUAL_HALO : HERMITE_SLAB_PRIMAL_HALO)
+                     : (s->half_steps & 1)            ? HERMITE_SLAB_DUAL_HALO
+                                                      : HERMITE_SLAB_PRIMAL_HALO;
     return HERMITE_OK;
+}
+
+int hermite_slab_half_step(hermite_slab* s, int* next_halo) {
+    return hermite_slab_half_step_part(s, HERMITE_SLAB_ALL, next_halo);
 }
 
 int hermite_slab_gather(hermite_slab* s, double* u, double* ut, double* t_out) {
     if (!s) return sfail(nullptr, HERMITE_EINVAL, "slab is NULL");
     if (!s->has_state) return sfail(s, HERMITE_ESTATE, "hermite_slab_gather before hermite_slab_set_initial");
-    if (s->half_steps & 1)
-        return sfail(s, HERMITE_ESTATE, "hermite_slab_gather after an odd number of half steps (%lld)", s->half_steps);
+    if ((s->half_steps & 1) || s->interior_done)
+        return sfail(s, HERMITE_ESTATE, "hermite_slab_gather inside a half step or after an odd number (%lld)",
+                     s->half_steps);
     int rc = slab_device(s);
     if (rc) return rc;
     const size_t rows = (size_t)s->M3, own = s->plane * s->nz, w = own * sizeof(double), sp = s->pitch * sizeof(double);
@@ -239,7 +273,7 @@ int hermite_slab_gather(hermite_slab* s, double* u, double* ut, double* t_out) {
     return HERMITE_OK;
 }
 
-int hermite_slab_copy_plane(hermite_slab* dst, int dst_which, hermite_slab* src, int src_which) {
+int hermite_slab_copy_plane(hermite_slab* dst, int dst_which, hermite_slab* src, int src_which, void* stream) {
     if (!dst || !src) return sfail(dst, HERMITE_EINVAL, "dst or src is NULL");
     if (dst->n != src->n || dst->M3 != src->M3)
         return sfail(dst, HERMITE_EINVAL, "slabs of different grids (n %d/%d, m %d/%d)", dst->n, src->n, dst->m, src->m);
@@ -251,7 +285,7 @@ int hermite_slab_copy_plane(hermite_slab* dst, int dst_which, hermite_slab* src,
     if ((rc = slab_device(dst)) != HERMITE_OK) return rc;
     SCHECK(dst,
            hipMemcpy2DAsync(d, dp, s, sp, dst->plane * sizeof(double), (size_t)2 * dst->M3, hipMemcpyDefault,
-                            dst->stream),
+                            stream ? (hipStream_t)stream : dst->stream),
            "plane copy");
     return HERMITE_OK;
 }

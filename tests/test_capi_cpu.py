@@ -218,6 +218,7 @@ def test_slab_null_calls_fail_cleanly():
     assert lib.hermite_slab_plane(None, 0, None, None) == B.HERMITE_EINVAL
     assert lib.hermite_slab_half_step(None, None) == B.HERMITE_EINVAL
     assert lib.hermite_slab_gather(None, None, None, None) == B.HERMITE_EINVAL
-    assert lib.hermite_slab_copy_plane(None, 0, None, 0) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_copy_plane(None, 0, None, 0, None) == B.HERMITE_EINVAL
+    assert lib.hermite_slab_half_step_part(None, 3, None) == B.HERMITE_EINVAL
     assert lib.hermite_slab_sync(None) == B.HERMITE_EINVAL
     lib.hermite_slab_destroy(None)

@@ -135,3 +135,79 @@ def test_slab_state_and_argument_errors():
             with pytest.raises(B.HermiteError) as e:
                 sl.copy_plane_from(B.HERMITE_SLAB_PRIMAL_HALO, other, B.HERMITE_SLAB_PRIMAL_FIRST)
             assert e.value.code == B.HERMITE_EINVAL
+
+
+def _run_slabs_split(n, splits, u0, ut0, steps, comm_stream=False):
+    """As _run_slabs, each half step in two parts: the interior cells, then
+    (after the halo copies) the boundary plane. With comm_stream the copies
+    run on a second stream, overlapping the interior parts, ordered by
+    events."""
+    stream = torch.cuda.Stream()
+    comm = torch.cuda.Stream() if comm_stream else None
+    z = np.cumsum([0] + list(splits))
+    slabs = [B.Slab(n, nz, stream=stream) for nz in splits]
+    try:
+        for g, sl in enumerate(slabs):
+            sl.set_initial(u0[:, :, :, z[g]:z[g + 1]], ut0[:, :, :, z[g]:z[g + 1]])
+        G = len(slabs)
+        for _ in range(2 * steps):
+            ready = torch.cuda.Event()
+            ready.record(stream)              # the planes to copy are final
+            halos = [sl.half_step_part(B.HERMITE_SLAB_INTERIOR) for sl in slabs]
+            cs = comm if comm_stream else stream
+            if comm_stream:
+                comm.wait_event(ready)
+            for g, sl in enumerate(slabs):
+                if halos[g] == B.HERMITE_SLAB_PRIMAL_HALO:
+                    sl.copy_plane_from(halos[g], slabs[(g + 1) % G], B.HERMITE_SLAB_PRIMAL_FIRST, stream=cs)
+                else:
+                    sl.copy_plane_from(halos[g], slabs[(g - 1) % G], B.HERMITE_SLAB_DUAL_LAST, stream=cs)
+            if comm_stream:
+                done = torch.cuda.Event()
+                done.record(comm)
+                stream.wait_event(done)
+            for sl in slabs:
+                sl.half_step_part(B.HERMITE_SLAB_BOUNDARY)
+        parts = [sl.gather() for sl in slabs]
+        return np.concatenate([p[0] for p in parts], axis=3), np.concatenate([p[1] for p in parts], axis=3)
+    finally:
+        for sl in slabs:
+            sl.close()
+
+
+@pytest.mark.parametrize("comm_stream", [False, True], ids=["one_stream", "copies_overlapping"])
+@pytest.mark.parametrize("splits", [(4, 4, 4), (1, 5, 6), (12,)])
+def test_split_half_steps_equal_the_cube(splits, comm_stream):
+    n = 12
+    rng = np.random.default_rng(40 + len(splits))
+    u0 = rng.standard_normal((4, 4, 4, n, n, n))
+    ut0 = rng.standard_normal((4, 4, 4, n, n, n))
+    print(f"[slab split] splits={splits} comm_stream={comm_stream}", flush=True)
+    su, sut = _run_slabs_split(n, splits, u0, ut0, 2, comm_stream)
+    cu, cut = _cube(n, u0, ut0, 2)
+    assert np.array_equal(su, cu) and np.array_equal(sut, cut)
+
+
+def test_split_part_order_errors():
+    n = 6
+    with B.Slab(n, 3) as sl:
+        z = np.zeros((4, 4, 4, 3, n, n))
+        sl.set_initial(z, z)
+        with pytest.raises(B.HermiteError) as e:
+            sl.half_step_part(B.HERMITE_SLAB_BOUNDARY)
+        assert e.value.code == B.HERMITE_ESTATE
+        assert sl.half_step_part(B.HERMITE_SLAB_INTERIOR) == B.HERMITE_SLAB_PRIMAL_HALO
+        for part in (B.HERMITE_SLAB_INTERIOR, B.HERMITE_SLAB_ALL):
+            with pytest.raises(B.HermiteError) as e:
+                sl.half_step_part(part)
+            assert e.value.code == B.HERMITE_ESTATE
+        with pytest.raises(B.HermiteError) as e:
+            sl.gather()
+        assert e.value.code == B.HERMITE_ESTATE
+        assert sl.half_step_part(B.HERMITE_SLAB_BOUNDARY) == B.HERMITE_SLAB_DUAL_HALO
+        assert sl.half_step_part(B.HERMITE_SLAB_INTERIOR) == B.HERMITE_SLAB_DUAL_HALO
+        assert sl.half_step_part(B.HERMITE_SLAB_BOUNDARY) == B.HERMITE_SLAB_PRIMAL_HALO
+        with pytest.raises(B.HermiteError) as e:
+            sl.half_step_part(0)
+        assert e.value.code == B.HERMITE_EINVAL
+        sl.gather()
