@@ -44,7 +44,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF-updates/s at m=3, plain FP64 vs mixed-precision at rel L2 <= 1e-6"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-MEASURED_FP64_MFMA_TFLOPS = 42.8  # v_mfma_f64_16x16x4f64 throughput measured on gfx950
+MEASURED_FP64_MFMA_TFLOPS = 68.9  # v_mfma_f64_4x4x4f64 (4 blocks) throughput measured on gfx950
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64, vector and matrix alike
 
 # Useful FP64 flops per cell per half step of the fused formulation: the
@@ -56,7 +56,7 @@ NNZ = {1: 255, 2: 2047, 3: 13499}
 # Source files of the m = 3 fused FP64 kernel; traffic counters taken on
 # another version of these files are not reported.
 MFMA_SOURCES = ["fused_mfma.hip", "fused_common.h", "mfma_order.h"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fused_mfma_128cube_m3.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fused_mfma4_128cube_m3.md")
 
 
 def fused_flops_per_cell(m: int) -> float:
@@ -523,7 +523,7 @@ def main():
             traffic = measured_traffic() if n == 128 else None
             roofline = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                        "kernel": "fused_mfma_kernel (FP64 MFMA 16x16x4)",
+                        "kernel": "fused_mfma4_kernel (FP64 MFMA 4x4x4, two z-adjacent batches per wave)",
                         # context: the FP64 MFMA rate measured on this chip by the committed
                         # microbenchmark (profiles/mfma_throughput_gfx950.md)
                         "measured_mfma_fp64_TFLOPs": MEASURED_FP64_MFMA_TFLOPS,

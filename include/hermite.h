@@ -55,13 +55,16 @@ extern "C" {
 #define HERMITE_PREC_FP32 1
 #define HERMITE_PREC_BF16X3 2
 
-/* Kernel of the fused FP64 half step at m = 3 (ignored otherwise). Both
- * compute the same contraction in FP64 with the same operator; on gfx950 the
- * matrix-core kernel is the faster one. */
-#define HERMITE_KERNEL_AUTO 0  /* the matrix-core kernel */
+/* Kernel of the fused FP64 half step at m = 3 (ignored otherwise). All
+ * compute the same contraction in FP64 with the same operator and give
+ * bit-identical results; on gfx950 the 4x4-tile matrix-core kernel is the
+ * fastest. Batches (hermite_batch_*) and slabs (hermite_slab_*) always run
+ * the 16x16 matrix-core kernel. */
+#define HERMITE_KERNEL_AUTO 0  /* the 4x4-tile matrix-core kernel */
 #define HERMITE_KERNEL_MFMA 1  /* FP64 matrix cores (v_mfma_f64_16x16x4) */
 #define HERMITE_KERNEL_VALU 2  /* FP64 vector FMAs, operator entries as scalar operands */
-#define HERMITE_KERNEL_MFMA4 3 /* FP64 matrix cores in 4x4 tiles (v_mfma_f64_4x4x4, 4 blocks) */
+#define HERMITE_KERNEL_MFMA4 3 /* FP64 matrix cores in 4x4 tiles (v_mfma_f64_4x4x4, 4 blocks),
+                                  two z-adjacent 16-cell batches per wave */
 
 /* Equation (Sec. 2). WAVE: u_tt = c^2 Lap u as the first-order system
  * (u, u_t), two fields per node. ADVECTION: u_t = c (u_x1 + u_x2 + u_x3),

@@ -269,7 +269,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
     e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipDeviceGetAttribute"));
     ctx->precision = o.precision;
-    ctx->m3_kernel = (o.kernel == HERMITE_KERNEL_VALU) ? 0 : (o.kernel == HERMITE_KERNEL_MFMA4) ? 2 : 1;
+    ctx->m3_kernel = (o.kernel == HERMITE_KERNEL_VALU) ? 0 : (o.kernel == HERMITE_KERNEL_MFMA) ? 1 : 2;
     std::vector<unsigned char> Kdev;
     if (nf == 1) {
         ctx->K1 = hermite::advection_axis_operator(m, ctx->lam);

@@ -131,6 +131,36 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
     }
 }
 
+// The sweep of the two-batch kernels, whose waves each take the cells of
+// rows (y, z) and (y, z + 1) (a row pair; f's last argument says whether the
+// second row belongs to this XCD's planes and is to be stored). Each XCD owns
+// its slab of z-planes as in sweep_rows, cut into nzp row-pair planes. The
+// batch positions (y, bx) of a plane, bx fastest, are dealt out in groups of
+// one per wave, so that rows whose batch count is not a multiple of the wave
+// count leave no wave idle. The XCD's items (row-pair plane, group) go round
+// robin to its G/8 workgroups in tiles of BZ planes x G/(8 BZ) consecutive
+// groups, BZ dividing nzp: the workgroups of one tile run at the same time on
+// neighbouring rows, every workgroup gets the same number of items (+-1), and
+// the items of a workgroup are all real. f(x0, y, z, upper) runs the pair at
+// x0 .. x0+15.
+template <class F>
+__device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves, F&& f) {
+    const uint32_t wpx = gridDim.x / 8;
+    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
+    const uint32_t nzp = (z1 - z0 + 1) / 2;
+    const uint32_t nbx = (n + 15) / 16, npos = n * nbx, NG = (npos + waves - 1) / waves;
+    const uint32_t BZ = (nzp % 4 == 0) ? 4 : (nzp % 2 == 0) ? 2 : 1;
+    const uint32_t NI = nzp * NG;
+    for (uint32_t i = w; i < NI; i += wpx) {
+        const uint32_t zz = i % BZ, rest = i / BZ, g = rest % NG, zp = (rest / NG) * BZ + zz;
+        const uint32_t pos = g * waves + wave;
+        if (pos >= npos) continue;
+        const uint32_t z = z0 + 2 * zp;
+        f((pos % nbx) * 16, pos / nbx, z, z + 1 < z1);
+    }
+}
+
 // The same sweep over the rows (y, k) of the cell planes k0 .. k1-1 of a
 // slab. A deep range is split among the XCDs along z as the cube is; a thin
 // one (fewer than 4 planes per XCD) along y, so that each XCD still sweeps a

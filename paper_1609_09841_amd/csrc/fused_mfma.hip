@@ -95,18 +95,57 @@ struct Steps {
 // output of column q for that cell), and D row i lands in quarter i at the
 // cell's lane. Per class, 4 instructions cover the 16 rows as row tiles ri
 // whose row i is class row 4i + ri, so quarter q accumulates class rows
-// 4q + ri, ri = 0..3: the 16x16 kernel's accumulator layout. The tile's 16
-// operator values are the same in all blocks; every block reads them from LDS.
+// 4q + ri, ri = 0..3: the 16x16 kernel's accumulator layout.
+//
+// A 16-cell batch alone would read 4x the operator values from LDS per cell
+// that the 16x16 kernel does (each tile's 16 values are the same in all 4
+// blocks). So each wave runs two batches at once, the cells (x, y, z) and
+// (x, y, z + 1): every operator tile read feeds both, and the lower corner
+// plane of the second cell is the upper corner plane of the first, so a step
+// loads 12 corner values instead of 16 (ra: the first cell's 8, rb: the
+// second cell's upper 4). Per step the wave issues 64 instructions, one class
+// after the other, with the next class's tiles already in flight.
+constexpr int kAhead4 = 2;
+constexpr int kRing4 = kAhead4 + 1;
+
+// Corner values s = 4 .. 7 (the upper z plane) of a cell, input column of step T.
 template <int T>
-struct Steps4 {
-    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& c,
-                                               const uint32_t* packed, int lane, const double* sK,
-                                               double (*acc)[4], double (*ring)[8]) {
+__device__ __forceinline__ void load_upper(const double* __restrict__ src, size_t plane, const Cell16& c,
+                                           const uint32_t* packed, double* v) {
+    const double* __restrict__ b = src + (size_t)step_col<T>(packed) * plane;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = b[c.corner[4 + s]];
+}
+
+// The first kAhead4 steps' corner values of a batch pair.
+template <int T>
+struct ProloguePair {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& ca,
+                                               const Cell16& cb, const uint32_t* packed, double (*ra)[8],
+                                               double (*rb)[4]) {
+        load_step<T>(src, plane, ca, packed, ra[T]);
+        load_upper<T>(src, plane, cb, packed, rb[T]);
+        if constexpr (T + 1 < kAhead4) ProloguePair<T + 1>::run(src, plane, ca, cb, packed, ra, rb);
+    }
+};
+
+template <int T>
+struct Steps4Pair {
+    __device__ __forceinline__ static void run(const double* __restrict__ src, size_t plane, const Cell16& ca,
+                                               const Cell16& cb, const uint32_t* packed, int lane, const double* sK,
+                                               double (*acca)[4], double (*accb)[4], double (*ra)[8],
+                                               double (*rb)[4]) {
         constexpr MfmaSchedule S{};
         constexpr int dp = S.dpar[T];
-        if constexpr (T + kAhead < 32) load_step<T + kAhead>(src, plane, c, packed, ring[(T + kAhead) % kRing]);
-        double Tv[8];
-        butterfly8(ring[T % kRing], Tv);
+        if constexpr (T + kAhead4 < 32) {
+            load_step<T + kAhead4>(src, plane, ca, packed, ra[(T + kAhead4) % kRing4]);
+            load_upper<T + kAhead4>(src, plane, cb, packed, rb[(T + kAhead4) % kRing4]);
+        }
+        double Ta[8], Tb[8], vb[8];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) vb[s] = ra[T % kRing4][4 + s], vb[4 + s] = rb[T % kRing4][s];
+        butterfly8(ra[T % kRing4], Ta);
+        butterfly8(vb, Tb);
         // this lane's A[i][k] (k = lane / 16, i = lane % 4) for row tiles
         // 2 rp and 2 rp + 1 of class p: one 16-byte read; a step's 32 tiles
         // are 4 KB, so every read of the step has an immediate offset
@@ -124,12 +163,14 @@ struct Steps4 {
 #pragma unroll
             for (int ri = 0; ri < 4; ++ri) {
                 const double2 av = a[p & 1][ri >> 1];
-                acc[p][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64((ri & 1) ? av.y : av.x, Tv[p ^ dp], acc[p][ri], 0,
-                                                                0, 0);
+                const double x = (ri & 1) ? av.y : av.x;
+                acca[p][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64(x, Ta[p ^ dp], acca[p][ri], 0, 0, 0);
+                accb[p][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64(x, Tb[p ^ dp], accb[p][ri], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (T + 1 < 32) Steps4<T + 1>::run(src, plane, c, packed, lane, sK, acc, ring);
+        if constexpr (T + 1 < 32)
+            Steps4Pair<T + 1>::run(src, plane, ca, cb, packed, lane, sK, acca, accb, ra, rb);
     }
 };
 
@@ -155,12 +196,31 @@ struct ColTable {
 };
 __constant__ ColTable kColTable = ColTable();
 
+// Stores the 32 new values a lane holds for one cell: logical output row 4q + r
+// of class p (register r of quarter q) is field q/2, derivative orders
+// j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2.
+template <class Acc>
+__device__ __forceinline__ void store_cell(double* __restrict__ dst, size_t plane, uint32_t out, int q,
+                                           const Acc& acc) {
+    const int fo = q >> 1, o3 = q & 1;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
+        const int j3 = p3 + 2 * o3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j1 = p1 + 2 * (r & 1), j2 = p2 + 2 * (r >> 1);
+            dst[(size_t)(fo * 64 + (j3 * 4 + j2) * 4 + j1) * plane + out] = acc[p][r];
+        }
+    }
+}
+
 // One batch: the 16 neighbouring cells of row (y, z) whose new nodes are
 // x0 .. x0+15 (lower corners x0 - off .., periodic); lanes past the end of
 // the row compute a copy of the last cell and store nothing.
 // SLAB: z is a buffer plane of a slab (fused::slab_cell_nodes) instead of a
 // plane of the periodic cube.
-template <bool SLAB = false, bool TILE4 = false>
+template <bool SLAB = false>
 __device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t plane,
                                           uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
                                           int cl, int q, uint32_t* packed, const double* sK) {
@@ -184,32 +244,35 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     for (int p = 0; p < 8; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
     double ring[kRing][8];
     Prologue<0>::run(src, plane, c, packed, ring);
-    if constexpr (TILE4) {
-        double acc4[8][4];
+    Steps<0>::run(src, plane, c, packed, lane, sK, acc, ring);
+    if (valid) store_cell(dst, plane, c.out, q, acc);
+}
+
+// Two batches of the cube on the 4x4-tile instruction: the 16 cells of row
+// (y, z) whose new nodes are x0 .. x0+15, as in run_batch, and the 16 cells
+// above them in row (y, z + 1) (periodic), stored only if upper is set.
+__device__ __forceinline__ void run_batch_pair(const double* __restrict__ src, double* __restrict__ dst,
+                                               size_t plane, uint32_t n, uint32_t off, uint32_t x0, uint32_t y,
+                                               uint32_t z, bool upper, int lane, int cl, int q, uint32_t* packed,
+                                               const double* sK) {
+    const uint32_t x = x0 + cl;
+    const bool valid = x < n;
+    const uint32_t cx = valid ? (x + n - off) % n : n - 1;
+    const uint32_t zb = (z + 1 == n) ? 0 : z + 1;
+    const Cell16 ca = cell_nodes((z * n + y) * n + cx, n, off);
+    const Cell16 cb = cell_nodes((zb * n + y) * n + cx, n, off);
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+    for (int w = 0; w < 8; ++w) asm volatile("" : "+v"(packed[w]));
+    double acca[8][4], accb[8][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc4[p][r] = 0.0;
-        Steps4<0>::run(src, plane, c, packed, lane, sK, acc4, ring);
+    for (int p = 0; p < 8; ++p)
 #pragma unroll
-        for (int p = 0; p < 8; ++p) acc[p] = d4{acc4[p][0], acc4[p][1], acc4[p][2], acc4[p][3]};
-    } else {
-        Steps<0>::run(src, plane, c, packed, lane, sK, acc, ring);
-    }
-    if (!valid) return;
-    // logical output row 4q + r of class p (register r of quarter q): field q/2,
-    // derivative orders j = p + 2 (o1, o2, o3) with o3 = q % 2, o2 = r / 2, o1 = r % 2
-    const int fo = q >> 1, o3 = q & 1;
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int p1 = p & 1, p2 = (p >> 1) & 1, p3 = p >> 2;
-        const int j3 = p3 + 2 * o3;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j1 = p1 + 2 * (r & 1), j2 = p2 + 2 * (r >> 1);
-            dst[(size_t)(fo * 64 + (j3 * 4 + j2) * 4 + j1) * plane + c.out] = acc[p][r];
-        }
-    }
+        for (int r = 0; r < 4; ++r) acca[p][r] = accb[p][r] = 0.0;
+    double ra[kRing4][8], rb[kRing4][4];
+    ProloguePair<0>::run(src, plane, ca, cb, packed, ra, rb);
+    Steps4Pair<0>::run(src, plane, ca, cb, packed, lane, sK, acca, accb, ra, rb);
+    if (valid) store_cell(dst, plane, ca.out, q, acca);
+    if (valid && upper) store_cell(dst, plane, cb.out, q, accb);
 }
 
 // Persistent kernel over the XCD-blocked row sweep (fused::sweep_rows).
@@ -230,12 +293,15 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_kernel(const double* _
     });
 }
 
-// The periodic cube on the 4x4-tile instruction (Steps4); operators from
-// mfma4_arrange_operators.
-__global__ __launch_bounds__(kWaves * 64) void fused_mfma4_kernel(const double* __restrict__ src,
-                                                                  double* __restrict__ dst,
-                                                                  const double* __restrict__ K4, uint32_t n,
-                                                                  size_t pitch, uint32_t off) {
+// The periodic cube on the 4x4-tile instruction, two z-adjacent batches per
+// wave (Steps4Pair); operators from mfma4_arrange_operators. The two
+// accumulator sets (128 registers) and the corner ring take more than half a
+// SIMD's registers, so the workgroup has one wave per SIMD.
+constexpr int kWaves4 = 4;
+
+__global__ __launch_bounds__(kWaves4 * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_mfma4_kernel(const double* __restrict__ src, double* __restrict__ dst, const double* __restrict__ K4,
+                        uint32_t n, size_t pitch, uint32_t off) {
     __shared__ double sK[kOpDoubles];
     for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = K4[i];
     __syncthreads();
@@ -244,8 +310,8 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma4_kernel(const double* 
     uint32_t packed[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
-    fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
-        run_batch<false, true>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
+    fused::sweep_row_pairs(n, wave, kWaves4, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
+        run_batch_pair(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q, packed, sK);
     });
 }
 
@@ -350,7 +416,7 @@ void mfma4_arrange_operators(const double* K, double* K4) {
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
                               hipStream_t st) {
     if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fused_mfma4_kernel, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, K4, (uint32_t)n, pitch,
+    hipLaunchKernelGGL(fused_mfma4_kernel, dim3(grid), dim3(kWaves4 * 64), 0, st, src, dst, K4, (uint32_t)n, pitch,
                        (uint32_t)off);
     return hipGetLastError();
 }
