@@ -40,6 +40,7 @@ struct hermite_ctx {
     size_t ncell = 0;                      // n^3 nodes per column
     size_t pitch = 0;                      // doubles between consecutive columns (>= ncell)
     void* K = nullptr;                     // fused class operators (layout of the kernel in use)
+    uint32_t* queue = nullptr;             // item counters of the 4x4-tile kernel (zero between launches)
     double* Hp = nullptr;                  // parity blocks of H
     size_t grid_doubles = 0;
     bool has_state = false;
@@ -95,6 +96,7 @@ void free_all(hermite_ctx* ctx) {
         if (g) { (void)hipFree(g); g = nullptr; }
     if (ctx->R) { (void)hipFree(ctx->R); ctx->R = nullptr; }
     if (ctx->K) { (void)hipFree(ctx->K); ctx->K = nullptr; }
+    if (ctx->queue) { (void)hipFree(ctx->queue); ctx->queue = nullptr; }
     if (ctx->Hp) { (void)hipFree(ctx->Hp); ctx->Hp = nullptr; }
     if (ctx->d_source) { (void)hipFree(ctx->d_source); ctx->d_source = nullptr; }
     if (ctx->d_source_prefix) { (void)hipFree(ctx->d_source_prefix); ctx->d_source_prefix = nullptr; }
@@ -136,7 +138,8 @@ int half_step(hermite_ctx* ctx, int from) {
         } else if (ctx->m == 3 && ctx->m3_kernel == 1) {
             e = hermite::launch_fused_mfma(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
         } else if (ctx->m == 3 && ctx->m3_kernel == 2) {
-            e = hermite::launch_fused_mfma4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
+            e = hermite::launch_fused_mfma4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->queue,
+                                            ctx->stream);
         } else if (ctx->m == 3) {
             e = hermite::launch_fused_valu4(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, ctx->stream);
         } else {
@@ -296,6 +299,14 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(K)"));
         e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
+    }
+    if (nf == 2 && o.precision == HERMITE_PREC_FP64 && m == 3 && o.fused && ctx->m3_kernel == 2) {
+        // the context's own work queue: contexts on different streams may run at once
+        const std::vector<uint32_t> zero(hermite::kMfma4QueueWords, 0u);
+        e = hipMalloc(&ctx->queue, zero.size() * sizeof(uint32_t));
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(queue)"));
+        e = hipMemcpy(ctx->queue, zero.data(), zero.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "clear queue"));
     }
     e = hipMalloc(&ctx->Hp, Hp.size() * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipMalloc(Hp)"));

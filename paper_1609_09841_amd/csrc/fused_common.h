@@ -137,27 +137,56 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
 // its slab of z-planes as in sweep_rows, cut into nzp row-pair planes. The
 // batch positions (y, bx) of a plane, bx fastest, are dealt out in groups of
 // one per wave, so that rows whose batch count is not a multiple of the wave
-// count leave no wave idle. The XCD's items (row-pair plane, group) go round
-// robin to its G/8 workgroups in tiles of BZ planes x G/(8 BZ) consecutive
-// groups, BZ dividing nzp: the workgroups of one tile run at the same time on
-// neighbouring rows, every workgroup gets the same number of items (+-1), and
-// the items of a workgroup are all real. f(x0, y, z, upper) runs the pair at
-// x0 .. x0+15.
+// count leave no wave idle. Items (row-pair plane, group) are numbered in
+// tiles of BZ planes (BZ dividing nzp) x consecutive groups, and the XCD's
+// workgroups take them from a counter in that order: the items in flight on
+// an XCD are always a window of consecutive ones, whose rows share node rows
+// in L2, however far the workgroups have drifted apart (a static round-robin
+// assignment let them drift and read 1.4x more). The workgroup's first wave
+// takes the next item while the current one runs.
+//
+// queue: 8 x 64 words, zero before the first launch; words 64 x and 64 x + 32
+// are XCD x's item counter and finished-workgroup counter. The last workgroup
+// of an XCD to finish sets both back to zero, so consecutive launches on one
+// stream need no reset; launches that run at the same time need queues of
+// their own. f(x0, y, z, upper) runs the pair at x0 .. x0+15.
 template <class F>
-__device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves, F&& f) {
+__device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves, uint32_t* queue, F&& f) {
     const uint32_t wpx = gridDim.x / 8;
-    const uint32_t xcd = blockIdx.x % 8, w = blockIdx.x / 8;
+    const uint32_t xcd = blockIdx.x % 8;
     const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
     const uint32_t nzp = (z1 - z0 + 1) / 2;
     const uint32_t nbx = (n + 15) / 16, npos = n * nbx, NG = (npos + waves - 1) / waves;
     const uint32_t BZ = (nzp % 4 == 0) ? 4 : (nzp % 2 == 0) ? 2 : 1;
     const uint32_t NI = nzp * NG;
-    for (uint32_t i = w; i < NI; i += wpx) {
+    uint32_t* ctr = queue + 64 * xcd;
+    uint32_t* done = ctr + 32;
+    // item numbers handed to the waves; the two slots alternate, so a slot is
+    // written only after every wave has passed the barrier that follows its read
+    __shared__ uint32_t s_item[2];
+    if (threadIdx.x == 0) s_item[0] = atomicAdd(ctr, 1u);
+    __syncthreads();
+    uint32_t i = s_item[0];
+    int slot = 0;
+    while (i < NI) {
+        uint32_t next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(ctr, 1u);
         const uint32_t zz = i % BZ, rest = i / BZ, g = rest % NG, zp = (rest / NG) * BZ + zz;
         const uint32_t pos = g * waves + wave;
-        if (pos >= npos) continue;
-        const uint32_t z = z0 + 2 * zp;
-        f((pos % nbx) * 16, pos / nbx, z, z + 1 < z1);
+        if (pos < npos) {
+            const uint32_t z = z0 + 2 * zp;
+            f((pos % nbx) * 16, pos / nbx, z, z + 1 < z1);
+        }
+        if (threadIdx.x == 0) s_item[slot ^ 1] = next;
+        __syncthreads();
+        slot ^= 1;
+        i = s_item[slot];
+    }
+    // every workgroup's last atomicAdd on ctr has returned before it counts
+    // itself here, so the last one to arrive can reset both
+    if (threadIdx.x == 0 && atomicAdd(done, 1u) == wpx - 1) {
+        atomicExch(ctr, 0u);
+        atomicExch(done, 0u);
     }
 }
 

@@ -301,7 +301,7 @@ constexpr int kWaves4 = 4;
 
 __global__ __launch_bounds__(kWaves4 * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void fused_mfma4_kernel(const double* __restrict__ src, double* __restrict__ dst, const double* __restrict__ K4,
-                        uint32_t n, size_t pitch, uint32_t off) {
+                        uint32_t n, size_t pitch, uint32_t off, uint32_t* __restrict__ queue) {
     __shared__ double sK[kOpDoubles];
     for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = K4[i];
     __syncthreads();
@@ -310,7 +310,7 @@ void fused_mfma4_kernel(const double* __restrict__ src, double* __restrict__ dst
     uint32_t packed[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
-    fused::sweep_row_pairs(n, wave, kWaves4, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
+    fused::sweep_row_pairs(n, wave, kWaves4, queue, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
         run_batch_pair(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q, packed, sK);
     });
 }
@@ -414,10 +414,10 @@ void mfma4_arrange_operators(const double* K, double* K4) {
 }
 
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
-                              hipStream_t st) {
-    if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
+                              uint32_t* queue, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0 || queue == nullptr) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fused_mfma4_kernel, dim3(grid), dim3(kWaves4 * 64), 0, st, src, dst, K4, (uint32_t)n, pitch,
-                       (uint32_t)off);
+                       (uint32_t)off, queue);
     return hipGetLastError();
 }
 

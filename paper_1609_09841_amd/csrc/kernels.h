@@ -27,10 +27,14 @@ hipError_t launch_fused_mfma(const double* src, double* dst, const double* Kperm
                              int grid, hipStream_t st);
 void mfma_permute_operators(const double* K, double* Kperm);
 size_t mfma_operator_doubles();
-// The same half step in 4x4 tiles (v_mfma_f64_4x4x4f64); K4 from
-// mfma4_arrange_operators (mfma_operator_doubles() doubles).
+// The same half step in 4x4 tiles (v_mfma_f64_4x4x4f64), two z-adjacent
+// batches per wave; K4 from mfma4_arrange_operators (mfma_operator_doubles()
+// doubles). queue: kMfma4QueueWords words of device memory, zero before the
+// first launch and left zero by every completed launch; launches that may
+// run at the same time need queues of their own.
+constexpr size_t kMfma4QueueWords = 8 * 64;
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
-                              hipStream_t st);
+                              uint32_t* queue, hipStream_t st);
 void mfma4_arrange_operators(const double* K, double* K4);
 // Cell planes k0 .. k1-1 (no launch if empty) of one z-slab of nz cell
 // planes of a periodic n x n x (shards * nz) grid: src and dst hold nz + 1

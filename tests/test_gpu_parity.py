@@ -330,3 +330,30 @@ def test_m3_matrix_kernels_bit_identical(n, evolution):
     mu, mv, _ = gpu_run(n, 3, u0, ut0, steps, fused=True, evolution=evolution, kernel="mfma")
     assert np.array_equal(tu, au) and np.array_equal(tv, av)
     assert np.array_equal(tu, mu) and np.array_equal(tv, mv)
+
+
+def test_m3_default_kernel_contexts_on_concurrent_streams():
+    """The default kernel's workgroups take their items from a work queue of
+    the context that resets itself at the end of every launch: two contexts
+    stepping at the same time on two streams, and one context over many
+    launches, give the 16x16 kernel's results bit for bit."""
+    import torch
+    n, steps = 24, 20
+    rng = np.random.default_rng(77)
+    data = [(rng.standard_normal((4, 4, 4, n, n, n)), rng.standard_normal((4, 4, 4, n, n, n))) for _ in range(2)]
+    ref = [gpu_run(n, 3, u0, ut0, steps, fused=True, kernel="mfma")[:2] for u0, ut0 in data]
+    print(f"[concurrent contexts] n={n} steps={steps}", flush=True)
+    streams = [torch.cuda.Stream() for _ in data]
+    solvers = [B.Solver(n, 3, stream=st) for st in streams]
+    try:
+        for s, (u0, ut0) in zip(solvers, data):
+            s.set_initial(u0, ut0)
+        for _ in range(steps):
+            for s in solvers:
+                s.step(1)
+        for s, (ru, rv) in zip(solvers, ref):
+            u, ut, _ = s.gather()
+            assert np.array_equal(u, ru) and np.array_equal(ut, rv)
+    finally:
+        for s in solvers:
+            s.close()
