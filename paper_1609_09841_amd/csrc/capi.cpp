@@ -133,7 +133,7 @@ int half_step(hermite_ctx* ctx, int from) {
     } else if (ctx->opt.fused) {
         const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
         if (ctx->precision != HERMITE_PREC_FP64) {
-            e = hermite::launch_fused_mixed(ctx->precision, src, dst, ctx->K, ctx->n, ctx->pitch, off, grid,
+            e = hermite::launch_fused_mixed(ctx->precision, src, dst, ctx->K, ctx->n, ctx->pitch, off, grid, ctx->queue,
                                             ctx->stream);
         } else if (ctx->m == 3 && ctx->m3_kernel == 1) {
             e = hermite::launch_fused_mfma(src, dst, (const double*)ctx->K, ctx->n, ctx->pitch, off, grid, ctx->stream);
@@ -300,7 +300,8 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
     }
-    if (nf == 2 && o.precision == HERMITE_PREC_FP64 && m == 3 && o.fused && ctx->m3_kernel == 2) {
+    if (nf == 2 && m == 3 && o.fused &&
+        ((o.precision == HERMITE_PREC_FP64 && ctx->m3_kernel == 2) || o.precision == HERMITE_PREC_FP32)) {
         // the context's own work queue: contexts on different streams may run at once
         const std::vector<uint32_t> zero(hermite::kMfma4QueueWords, 0u);
         e = hipMalloc(&ctx->queue, zero.size() * sizeof(uint32_t));

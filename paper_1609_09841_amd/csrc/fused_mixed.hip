@@ -15,7 +15,8 @@
 //
 // FP32: v_mfma_f32_16x16x4f32, one K-step per input column chunk, the same
 // shape as the FP64 kernel (A = operator rows x 4 columns, B = 4 columns x 16
-// cells; register r of lane quarter q holds row 4q + r).
+// cells; register r of lane quarter q holds row 4q + r). A single grid runs
+// two z-adjacent batches per wave (StepsF32Pair); batches of shots one.
 // BF16x3: v_mfma_f32_16x16x16_bf16 over 8 K-steps of 16 columns (lane
 // quarter q supplies k = 4q .. 4q+3). Operator and inputs are split into a
 // high and a low BF16 part (x = x_hi + x_lo, each round-to-nearest-even) and
@@ -90,6 +91,68 @@ struct StepsF32 {
             acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p], (float)Tv[p ^ dp], acc[p], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (T + 1 < 32) StepsF32<T + 1>::run(base, pitch, c, lane, sA, acc, P0, ring);
+    }
+};
+
+// Two batches per wave, the cells (x, y, z) and (x, y, z + 1), as in the FP64
+// 4x4-tile kernel: every operator value read from LDS feeds both, and the
+// lower corner plane of the second cell is the upper plane of the first, so
+// a step loads 12 corner values (ra: the first cell's 8, rb: the second
+// cell's upper 4) instead of 16. A step's matrix work is short in FP32, and
+// with one wave per SIMD only the prefetch hides the gathers: kAheadPair
+// steps are in flight.
+constexpr int kAheadPair = 4;
+constexpr int kRingPair = kAheadPair + 1;
+template <int T>
+__device__ __forceinline__ void load_own_upper(const double* __restrict__ base, size_t pitch, const Cell16& c,
+                                               double* v) {
+    constexpr OwnSchedule S{};
+    const double* __restrict__ b = base + (size_t)S.u[T] * pitch;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = b[c.corner[4 + s]];
+}
+
+template <int T>
+struct PrologueF32Pair {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& ca,
+                                               const Cell16& cb, double (*ra)[8], double (*rb)[4]) {
+        load_own<T>(base, pitch, ca, ra[T]);
+        load_own_upper<T>(base, pitch, cb, rb[T]);
+        if constexpr (T + 1 < kAheadPair) PrologueF32Pair<T + 1>::run(base, pitch, ca, cb, ra, rb);
+    }
+};
+
+template <int T>
+struct StepsF32Pair {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& ca,
+                                               const Cell16& cb, int lane, const float* sA, f4* acca, f4* accb,
+                                               double (*P0a)[4], double (*P0b)[4], double (*ra)[8],
+                                               double (*rb)[4]) {
+        constexpr OwnSchedule S{};
+        constexpr int u = S.u[T], dp = OwnSchedule::parity(u), rg = OwnSchedule::reg(u);
+        constexpr int AH = kAheadPair;
+        if constexpr (T + AH < 32) {
+            load_own<T + AH>(base, pitch, ca, ra[(T + AH) % kRingPair]);
+            load_own_upper<T + AH>(base, pitch, cb, rb[(T + AH) % kRingPair]);
+        }
+        double Ta[8], Tb[8], vb[8];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) vb[s] = ra[T % kRingPair][4 + s], vb[4 + s] = rb[T % kRingPair][s];
+        butterfly8(ra[T % kRingPair], Ta);
+        butterfly8(vb, Tb);
+        P0a[dp][rg] = 0.125 * Ta[0];
+        P0b[dp][rg] = 0.125 * Tb[0];
+        float a[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) a[p] = sA[(p * 32 + T) * 64 + lane];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            acca[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p], (float)Ta[p ^ dp], acca[p], 0, 0, 0);
+            accb[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p], (float)Tb[p ^ dp], accb[p], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (T + 1 < 32)
+            StepsF32Pair<T + 1>::run(base, pitch, ca, cb, lane, sA, acca, accb, P0a, P0b, ra, rb);
     }
 };
 
@@ -177,6 +240,31 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     if (valid) store_batch(dst, pitch, c, q, acc, P0);
 }
 
+// FP32: the batch of row (y, z) and the one above it, row (y, z + 1)
+// (periodic), stored only if upper is set.
+__device__ __forceinline__ void run_batch_pair_f32(const double* __restrict__ src, double* __restrict__ dst,
+                                                   size_t pitch, uint32_t n, uint32_t off, uint32_t x0, uint32_t y,
+                                                   uint32_t z, bool upper, int lane, int cl, int q,
+                                                   const float* sA) {
+    const uint32_t x = x0 + cl;
+    const bool valid = x < n;
+    const uint32_t cx = valid ? (x + n - off) % n : n - 1;
+    const uint32_t zb = (z + 1 == n) ? 0 : z + 1;
+    const Cell16 ca = cell_nodes((z * n + y) * n + cx, n, off);
+    const Cell16 cb = cell_nodes((zb * n + y) * n + cx, n, off);
+    const double* base = src + (size_t)(32 * q) * pitch;
+    asm volatile("" : "+v"(base));
+    f4 acca[8], accb[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acca[p] = accb[p] = f4{0.f, 0.f, 0.f, 0.f};
+    double P0a[8][4], P0b[8][4];
+    double ra[kRingPair][8], rb[kRingPair][4];
+    PrologueF32Pair<0>::run(base, pitch, ca, cb, ra, rb);
+    StepsF32Pair<0>::run(base, pitch, ca, cb, lane, sA, acca, accb, P0a, P0b, ra, rb);
+    if (valid) store_batch(dst, pitch, ca, q, acca, P0a);
+    if (valid && upper) store_batch(dst, pitch, cb, q, accb, P0b);
+}
+
 template <int PREC>
 __device__ __forceinline__ void load_operator(const void* __restrict__ Aops, unsigned char* sbuf) {
     constexpr int kBytes = (PREC == 1) ? kF32Floats * 4 : kBf16Vecs * 8;
@@ -200,6 +288,24 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mixed_kernel(const double* 
     const int cl = lane & 15, q = lane >> 4;
     fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
         run_batch<PREC>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, sbuf);
+    });
+}
+
+// FP32 on a single grid: two z-adjacent batches per wave (StepsF32Pair) over
+// the queue-fed row-pair sweep (fused::sweep_row_pairs). The second set of
+// accumulators and P0 values takes the registers of a second wave: one wave
+// per SIMD, four per workgroup.
+constexpr int kWavesPair = 4;
+
+__global__ __launch_bounds__(kWavesPair * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_f32_pair_kernel(const double* __restrict__ src, double* __restrict__ dst, const void* __restrict__ Aops,
+                           uint32_t n, size_t pitch, uint32_t off, uint32_t* __restrict__ queue) {
+    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<1>];
+    load_operator<1>(Aops, sbuf);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    fused::sweep_row_pairs(n, wave, kWavesPair, queue, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
+        run_batch_pair_f32(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q, (const float*)sbuf);
     });
 }
 
@@ -293,11 +399,12 @@ hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots,
 }
 
 hipError_t launch_fused_mixed(int precision, const double* src, double* dst, const void* Aops, int n, size_t pitch,
-                              int off, int grid, hipStream_t st) {
+                              int off, int grid, uint32_t* queue, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
+    if (precision == 1 && queue == nullptr) return hipErrorInvalidValue;
     if (precision == 1)
-        hipLaunchKernelGGL(fused_mixed_kernel<1>, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Aops, (uint32_t)n,
-                           pitch, (uint32_t)off);
+        hipLaunchKernelGGL(fused_f32_pair_kernel, dim3(grid), dim3(kWavesPair * 64), 0, st, src, dst, Aops,
+                           (uint32_t)n, pitch, (uint32_t)off, queue);
     else if (precision == 2)
         hipLaunchKernelGGL(fused_mixed_kernel<2>, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Aops, (uint32_t)n,
                            pitch, (uint32_t)off);

@@ -65,8 +65,10 @@ bool valu_small_build_operators(int m, const double* K, double* Kv);
 // 2 = split BF16 (three products), both with FP32 accumulation; FP64 state,
 // FP64 corner-mean part and FP64 update. Aops: mixed_build_operators output
 // (mixed_operator_bytes(precision) bytes). grid as for launch_fused_mfma.
+// FP32 runs two z-adjacent batches per wave and needs a queue as
+// launch_fused_mfma4 does (kMfma4QueueWords words); BF16x3 ignores it.
 hipError_t launch_fused_mixed(int precision, const double* src, double* dst, const void* Aops, int n, size_t pitch,
-                              int off, int grid, hipStream_t st);
+                              int off, int grid, uint32_t* queue, hipStream_t st);
 size_t mixed_operator_bytes(int precision);
 void mixed_build_operators(int precision, const double* K, void* out);
 
