@@ -149,14 +149,15 @@ __device__ __forceinline__ void sweep_rows(uint32_t n, int wave, int waves, F&& 
 // are XCD x's item counter and finished-workgroup counter. The last workgroup
 // of an XCD to finish sets both back to zero, so consecutive launches on one
 // stream need no reset; launches that run at the same time need queues of
-// their own. f(x0, y, z, upper) runs the pair at x0 .. x0+15.
+// their own. This XCD's rows are y0 .. y1-1 of planes z0 .. z1-1; f(x0, y, z,
+// upper) runs the pair at x0 .. x0+15.
 template <class F>
-__device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves, uint32_t* queue, F&& f) {
+__device__ __forceinline__ void sweep_row_pairs_in(uint32_t n, uint32_t y0, uint32_t y1, uint32_t z0, uint32_t z1,
+                                                   int wave, int waves, uint32_t* queue, F&& f) {
     const uint32_t wpx = gridDim.x / 8;
     const uint32_t xcd = blockIdx.x % 8;
-    const uint32_t z0 = xcd * n / 8, z1 = (xcd + 1) * n / 8;
     const uint32_t nzp = (z1 - z0 + 1) / 2;
-    const uint32_t nbx = (n + 15) / 16, npos = n * nbx, NG = (npos + waves - 1) / waves;
+    const uint32_t nbx = (n + 15) / 16, npos = (y1 - y0) * nbx, NG = (npos + waves - 1) / waves;
     const uint32_t BZ = (nzp % 4 == 0) ? 4 : (nzp % 2 == 0) ? 2 : 1;
     const uint32_t NI = nzp * NG;
     uint32_t* ctr = queue + 64 * xcd;
@@ -175,7 +176,7 @@ __device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves,
         const uint32_t pos = g * waves + wave;
         if (pos < npos) {
             const uint32_t z = z0 + 2 * zp;
-            f((pos % nbx) * 16, pos / nbx, z, z + 1 < z1);
+            f((pos % nbx) * 16, y0 + pos / nbx, z, z + 1 < z1);
         }
         if (threadIdx.x == 0) s_item[slot ^ 1] = next;
         __syncthreads();
@@ -188,6 +189,25 @@ __device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves,
         atomicExch(ctr, 0u);
         atomicExch(done, 0u);
     }
+}
+
+// The periodic cube: XCD x owns planes x n / 8 .. (x + 1) n / 8 - 1.
+template <class F>
+__device__ __forceinline__ void sweep_row_pairs(uint32_t n, int wave, int waves, uint32_t* queue, F&& f) {
+    const uint32_t xcd = blockIdx.x % 8;
+    sweep_row_pairs_in(n, 0, n, xcd * n / 8, (xcd + 1) * n / 8, wave, waves, queue, f);
+}
+
+// The cell planes k0 .. k1-1 of a slab, split among the XCDs as in
+// sweep_rows_slab: along z when deep, along y when thin.
+template <class F>
+__device__ __forceinline__ void sweep_row_pairs_slab(uint32_t n, uint32_t k0, uint32_t k1, int wave, int waves,
+                                                     uint32_t* queue, F&& f) {
+    const uint32_t xcd = blockIdx.x % 8, nz = k1 - k0;
+    if (nz >= 32)
+        sweep_row_pairs_in(n, 0, n, k0 + xcd * nz / 8, k0 + (xcd + 1) * nz / 8, wave, waves, queue, f);
+    else
+        sweep_row_pairs_in(n, xcd * n / 8, (xcd + 1) * n / 8, k0, k1, wave, waves, queue, f);
 }
 
 // The same sweep over the rows (y, k) of the cell planes k0 .. k1-1 of a

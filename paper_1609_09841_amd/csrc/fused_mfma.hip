@@ -248,9 +248,13 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     if (valid) store_cell(dst, plane, c.out, q, acc);
 }
 
-// Two batches of the cube on the 4x4-tile instruction: the 16 cells of row
-// (y, z) whose new nodes are x0 .. x0+15, as in run_batch, and the 16 cells
-// above them in row (y, z + 1) (periodic), stored only if upper is set.
+// Two batches on the 4x4-tile instruction: the 16 cells of row (y, z) whose
+// new nodes are x0 .. x0+15, as in run_batch, and the 16 cells above them in
+// row (y, z + 1) (periodic in the cube), stored only if upper is set.
+// SLAB: z is a buffer plane of a slab; without upper, the second batch
+// repeats the first (plane z + 1 may lie past the slab's buffer) and is not
+// stored.
+template <bool SLAB = false>
 __device__ __forceinline__ void run_batch_pair(const double* __restrict__ src, double* __restrict__ dst,
                                                size_t plane, uint32_t n, uint32_t off, uint32_t x0, uint32_t y,
                                                uint32_t z, bool upper, int lane, int cl, int q, uint32_t* packed,
@@ -258,9 +262,15 @@ __device__ __forceinline__ void run_batch_pair(const double* __restrict__ src, d
     const uint32_t x = x0 + cl;
     const bool valid = x < n;
     const uint32_t cx = valid ? (x + n - off) % n : n - 1;
-    const uint32_t zb = (z + 1 == n) ? 0 : z + 1;
-    const Cell16 ca = cell_nodes((z * n + y) * n + cx, n, off);
-    const Cell16 cb = cell_nodes((zb * n + y) * n + cx, n, off);
+    Cell16 ca, cb;
+    if constexpr (SLAB) {
+        ca = fused::slab_cell_nodes(cx, y, z, n, off);
+        cb = fused::slab_cell_nodes(cx, y, upper ? z + 1 : z, n, off);
+    } else {
+        const uint32_t zb = (z + 1 == n) ? 0 : z + 1;
+        ca = cell_nodes((z * n + y) * n + cx, n, off);
+        cb = cell_nodes((zb * n + y) * n + cx, n, off);
+    }
 #pragma unroll
     for (int w = 0; w < 8; ++w) asm volatile("" : "+v"(packed[w]));
     double acca[8][4], accb[8][4];
@@ -333,6 +343,27 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_slab_kernel(const doub
     fused::sweep_rows_slab(n, k0, k1, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
         run_batch<true>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, packed, sK);
     });
+}
+
+// The cell planes k0 .. k1-1 of a slab on the 4x4-tile instruction, two
+// z-adjacent batches per wave (fused::sweep_row_pairs_slab).
+__global__ __launch_bounds__(kWaves4 * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_mfma4_slab_kernel(const double* __restrict__ src, double* __restrict__ dst, const double* __restrict__ K4,
+                             uint32_t n, uint32_t k0, uint32_t k1, size_t pitch, uint32_t off,
+                             uint32_t* __restrict__ queue) {
+    __shared__ double sK[kOpDoubles];
+    for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = K4[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    uint32_t packed[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
+    fused::sweep_row_pairs_slab(n, k0, k1, wave, kWaves4, queue,
+                                [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
+                                    run_batch_pair<true>(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q,
+                                                         packed, sK);
+                                });
 }
 
 // Batched: the 16-cell batches of every shot of the group (batch_common.h).
@@ -411,6 +442,15 @@ void mfma4_arrange_operators(const double* K, double* K4) {
                     for (int i = 0; i < 4; ++i)
                         K4[((((size_t)t * 8 + p) * 2 + (ri >> 1)) * 16 + 4 * k + i) * 2 + (ri & 1)] =
                             K[((size_t)p * 16 + 4 * i + ri) * 128 + S.col[t][k]];
+}
+
+hipError_t launch_fused_mfma4_slab(const double* src, double* dst, const double* K4, int n, int k0, int k1,
+                                   size_t pitch, int off, int grid, uint32_t* queue, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0 || k0 < 0 || k1 < k0 || queue == nullptr) return hipErrorInvalidValue;
+    if (k1 == k0) return hipSuccess;
+    hipLaunchKernelGGL(fused_mfma4_slab_kernel, dim3(grid), dim3(kWaves4 * 64), 0, st, src, dst, K4, (uint32_t)n,
+                       (uint32_t)k0, (uint32_t)k1, pitch, (uint32_t)off, queue);
+    return hipGetLastError();
 }
 
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,

@@ -36,6 +36,11 @@ constexpr size_t kMfma4QueueWords = 8 * 64;
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
                               uint32_t* queue, hipStream_t st);
 void mfma4_arrange_operators(const double* K, double* K4);
+// Cell planes k0 .. k1-1 (no launch if empty) of a z-slab on the 4x4-tile
+// instruction, two z-adjacent batches per wave; K4 and queue as for
+// launch_fused_mfma4.
+hipError_t launch_fused_mfma4_slab(const double* src, double* dst, const double* K4, int n, int k0, int k1,
+                                   size_t pitch, int off, int grid, uint32_t* queue, hipStream_t st);
 // Cell planes k0 .. k1-1 (no launch if empty) of one z-slab of nz cell
 // planes of a periodic n x n x (shards * nz) grid: src and dst hold nz + 1
 // node planes of n^2 nodes per column (the slab layout of

@@ -36,7 +36,9 @@ struct hermite_slab {
     double* grid[2] = {nullptr, nullptr};  // primal, dual: 2 M^3 columns of `pitch` doubles
     size_t plane = 0;                      // n^2 nodes per plane
     size_t pitch = 0;
-    void* K = nullptr;                     // class operators, matrix-core layout
+    void* K = nullptr;                     // class operators, 16x16-tile layout (the boundary plane)
+    void* K4 = nullptr;                    // the same, 4x4-tile layout (interior and whole half steps)
+    uint32_t* queue = nullptr;             // item counters of the 4x4-tile kernel (zero between launches)
     bool has_state = false;
     long long half_steps = 0;
     bool interior_done = false;            // the current half step's interior cells are enqueued
@@ -74,6 +76,8 @@ void free_slab(hermite_slab* s) {
     for (double*& g : s->grid)
         if (g) { (void)hipFree(g); g = nullptr; }
     if (s->K) { (void)hipFree(s->K); s->K = nullptr; }
+    if (s->K4) { (void)hipFree(s->K4); s->K4 = nullptr; }
+    if (s->queue) { (void)hipFree(s->queue); s->queue = nullptr; }
     if (s->own_stream && s->stream) { (void)hipStreamDestroy(s->stream); s->stream = nullptr; }
 }
 
@@ -165,6 +169,17 @@ int hermite_slab_create(int n_cells, int nz, int m, double cfl, double c, const 
     if (e != hipSuccess) return bail(shipfail(s, e, "hipMalloc(K)"));
     e = hipMemcpy(s->K, Kperm.data(), Kperm.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(shipfail(s, e, "upload K"));
+    std::vector<double> K4(hermite::mfma_operator_doubles());
+    hermite::mfma4_arrange_operators(K.data(), K4.data());
+    e = hipMalloc(&s->K4, K4.size() * sizeof(double));
+    if (e != hipSuccess) return bail(shipfail(s, e, "hipMalloc(K4)"));
+    e = hipMemcpy(s->K4, K4.data(), K4.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(shipfail(s, e, "upload K4"));
+    const std::vector<uint32_t> zero(hermite::kMfma4QueueWords, 0u);
+    e = hipMalloc(&s->queue, zero.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return bail(shipfail(s, e, "hipMalloc(queue)"));
+    e = hipMemcpy(s->queue, zero.data(), zero.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(shipfail(s, e, "clear queue"));
     *out = s;
     return HERMITE_OK;
 }
@@ -228,10 +243,19 @@ int hermite_slab_half_step_part(hermite_slab* s, int part, int* next_halo) {
         k0 = kb;
         k1 = kb + 1;
     }
-    SCHECK(s,
-           hermite::launch_fused_mfma_slab(s->grid[from], s->grid[1 - from], (const double*)s->K, s->n, k0, k1,
-                                           s->pitch, from, s->grid_blocks, s->stream),
-           "slab half-step launch");
+    // several planes: two z-adjacent batches per wave (4x4 tiles); the single
+    // boundary plane: one batch per wave (16x16 tiles), which a plane without
+    // a partner does not leave half idle. Both give bit-identical results.
+    if (part == HERMITE_SLAB_BOUNDARY)
+        SCHECK(s,
+               hermite::launch_fused_mfma_slab(s->grid[from], s->grid[1 - from], (const double*)s->K, s->n, k0, k1,
+                                               s->pitch, from, s->grid_blocks, s->stream),
+               "slab boundary-plane launch");
+    else
+        SCHECK(s,
+               hermite::launch_fused_mfma4_slab(s->grid[from], s->grid[1 - from], (const double*)s->K4, s->n, k0,
+                                                k1, s->pitch, from, s->grid_blocks, s->queue, s->stream),
+               "slab half-step launch");
     if (part == HERMITE_SLAB_INTERIOR) {
         s->interior_done = true;
     } else {
