@@ -366,28 +366,30 @@ void fused_mfma4_slab_kernel(const double* __restrict__ src, double* __restrict_
                                 });
 }
 
-// Batched: the 16-cell batches of every shot of the group (batch_common.h).
-__global__ __launch_bounds__(kWaves * 64) void fused_mfma_batch_kernel(const batch::ShotGrid* __restrict__ shots,
-                                                                       const uint32_t* __restrict__ ids,
-                                                                       const uint32_t* __restrict__ prefix,
-                                                                       uint32_t ng, uint32_t from,
-                                                                       const double* __restrict__ Kperm,
-                                                                       uint32_t chunk, uint32_t interleaved) {
+// Batched: the batch pairs of every shot of the group (batch_common.h) on the
+// 4x4-tile instruction. A shot of n cells per side has n ceil(n/2) ceil(n/16)
+// items: item (bx, y, zp), bx fastest, is the pair of rows (y, 2 zp) and
+// (y, 2 zp + 1) at x-batch bx (the second row absent when n is odd and
+// 2 zp + 1 = n).
+__global__ __launch_bounds__(kWaves4 * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_mfma_batch_kernel(const batch::ShotGrid* __restrict__ shots, const uint32_t* __restrict__ ids,
+                             const uint32_t* __restrict__ prefix, uint32_t ng, uint32_t from,
+                             const double* __restrict__ K4, uint32_t chunk, uint32_t interleaved) {
     __shared__ double sK[kOpDoubles];
-    for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = Kperm[i];
+    for (int i = threadIdx.x; i < kOpDoubles; i += blockDim.x) sK[i] = K4[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
     uint32_t packed[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) packed[k] = kColTable.w[q][k];
-    batch::sweep_items(prefix[ng], wave, kWaves, chunk, interleaved, [&](uint32_t it) {
+    batch::sweep_items(prefix[ng], wave, kWaves4, chunk, interleaved, [&](uint32_t it) {
         const uint32_t g = batch::find_entry(prefix, ng, it);
         const batch::ShotGrid& S = shots[ids[g]];
         const uint32_t n = S.n, nbx = (n + 15) >> 4, local = it - prefix[g];
-        const uint32_t bx = local % nbx, row = local / nbx;
-        run_batch(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, row % n, row / n, lane, cl, q, packed,
-                  sK);
+        const uint32_t bx = local % nbx, rest = local / nbx, y = rest % n, z = 2 * (rest / n);
+        run_batch_pair(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, y, z, z + 1 < n, lane, cl, q,
+                       packed, sK);
     });
 }
 
@@ -396,11 +398,11 @@ __global__ __launch_bounds__(kWaves * 64) void fused_mfma_batch_kernel(const bat
 size_t mfma_operator_doubles() { return (size_t)kOpDoubles; }
 
 hipError_t launch_fused_mfma_batch(const batch::ShotGrid* shots, const uint32_t* ids, const uint32_t* prefix,
-                                   uint32_t ng, int from, const double* Kperm, int grid, uint32_t chunk,
+                                   uint32_t ng, int from, const double* K4, int grid, uint32_t chunk,
                                    uint32_t interleaved, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0 || chunk < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fused_mfma_batch_kernel, dim3(grid), dim3(kWaves * 64), 0, st, shots, ids, prefix, ng,
-                       (uint32_t)from, Kperm, chunk, interleaved);
+    hipLaunchKernelGGL(fused_mfma_batch_kernel, dim3(grid), dim3(kWaves4 * 64), 0, st, shots, ids, prefix, ng,
+                       (uint32_t)from, K4, chunk, interleaved);
     return hipGetLastError();
 }
 

@@ -142,8 +142,11 @@ struct ShotGrid;
 hipError_t launch_fused_valu_small_batch(int m, int block, const batch::ShotGrid* shots, const uint32_t* ids,
                                          const uint32_t* prefix, uint32_t ng, uint32_t blocks, int from,
                                          const double* Kv, hipStream_t st);
+// FP64 m = 3 batches run two z-adjacent batches per wave on the 4x4-tile
+// instruction: K4 from mfma4_arrange_operators, and prefix counts
+// n ceil(n/2) ceil(n/16) items per shot.
 hipError_t launch_fused_mfma_batch(const batch::ShotGrid* shots, const uint32_t* ids, const uint32_t* prefix,
-                                   uint32_t ng, int from, const double* Kperm, int grid, uint32_t chunk,
+                                   uint32_t ng, int from, const double* K4, int grid, uint32_t chunk,
                                    uint32_t interleaved, hipStream_t st);
 hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots, const uint32_t* ids,
                                     const uint32_t* prefix, uint32_t ng, int from, const void* Aops, int grid,
