@@ -59,7 +59,7 @@ extern "C" {
  * compute the same contraction in FP64 with the same operator and give
  * bit-identical results; on gfx950 the 4x4-tile matrix-core kernel is the
  * fastest. Batches (hermite_batch_*) and slabs (hermite_slab_*) always run
- * the 16x16 matrix-core kernel. */
+ * the 4x4-tile kernel (a slab's lone boundary plane the 16x16 one). */
 #define HERMITE_KERNEL_AUTO 0  /* the 4x4-tile matrix-core kernel */
 #define HERMITE_KERNEL_MFMA 1  /* FP64 matrix cores (v_mfma_f64_16x16x4) */
 #define HERMITE_KERNEL_VALU 2  /* FP64 vector FMAs, operator entries as scalar operands */

@@ -16,7 +16,8 @@
 // FP32: v_mfma_f32_16x16x4f32, one K-step per input column chunk, the same
 // shape as the FP64 kernel (A = operator rows x 4 columns, B = 4 columns x 16
 // cells; register r of lane quarter q holds row 4q + r). A single grid runs
-// two z-adjacent batches per wave (StepsF32Pair); batches of shots one.
+// two z-adjacent batches per wave (StepsF32Pair), on a single grid and in
+// batches of shots.
 // BF16x3: v_mfma_f32_16x16x16_bf16 over 8 K-steps of 16 columns (lane
 // quarter q supplies k = 4q .. 4q+3). Operator and inputs are split into a
 // high and a low BF16 part (x = x_hi + x_lo, each round-to-nearest-even) and
@@ -71,29 +72,6 @@ struct Prologue {
 };
 
 // ---------------------------------------------------------------- FP32
-template <int T>
-struct StepsF32 {
-    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& c,
-                                               int lane, const float* sA, f4* acc, double (*P0)[4],
-                                               double (*ring)[8]) {
-        constexpr OwnSchedule S{};
-        constexpr int u = S.u[T], dp = OwnSchedule::parity(u), rg = OwnSchedule::reg(u);
-        constexpr int AH = kAhead<1>;
-        if constexpr (T + AH < 32) load_own<T + AH>(base, pitch, c, ring[(T + AH) % kRing]);
-        double Tv[8];
-        butterfly8(ring[T % kRing], Tv);
-        P0[dp][rg] = 0.125 * Tv[0];
-        float a[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) a[p] = sA[(p * 32 + T) * 64 + lane];
-#pragma unroll
-        for (int p = 0; p < 8; ++p)
-            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p], (float)Tv[p ^ dp], acc[p], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (T + 1 < 32) StepsF32<T + 1>::run(base, pitch, c, lane, sA, acc, P0, ring);
-    }
-};
-
 // Two batches per wave, the cells (x, y, z) and (x, y, z + 1), as in the FP64
 // 4x4-tile kernel: every operator value read from LDS feeds both, and the
 // lower corner plane of the second cell is the upper plane of the first, so
@@ -231,12 +209,9 @@ __device__ __forceinline__ void run_batch(const double* __restrict__ src, double
     double P0[8][4];
     double ring[kRing][8];
     Prologue<kAhead<PREC>, 0>::run(base, pitch, c, ring);
-    if constexpr (PREC == 1) {
-        StepsF32<0>::run(base, pitch, c, lane, (const float*)sbuf, acc, P0, ring);
-    } else {
-        s4 Bhi[8], Blo[8];
-        StepsBf16<0>::run(base, pitch, c, lane, (const s4*)sbuf, acc, P0, ring, Bhi, Blo);
-    }
+    static_assert(PREC == 2, "FP32 runs batch pairs (run_batch_pair_f32)");
+    s4 Bhi[8], Blo[8];
+    StepsBf16<0>::run(base, pitch, c, lane, (const s4*)sbuf, acc, P0, ring, Bhi, Blo);
     if (valid) store_batch(dst, pitch, c, q, acc, P0);
 }
 
@@ -306,6 +281,27 @@ void fused_f32_pair_kernel(const double* __restrict__ src, double* __restrict__ 
     const int cl = lane & 15, q = lane >> 4;
     fused::sweep_row_pairs(n, wave, kWavesPair, queue, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
         run_batch_pair_f32(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q, (const float*)sbuf);
+    });
+}
+
+// FP32 batches of shots: item (bx, y, zp) of a shot, bx fastest, is the pair
+// of rows (y, 2 zp) and (y, 2 zp + 1) at x-batch bx (n ceil(n/2) ceil(n/16)
+// items per shot, the FP64 batch kernel's numbering).
+__global__ __launch_bounds__(kWavesPair * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_f32_pair_batch_kernel(const batch::ShotGrid* __restrict__ shots, const uint32_t* __restrict__ ids,
+                                 const uint32_t* __restrict__ prefix, uint32_t ng, uint32_t from,
+                                 const void* __restrict__ Aops, uint32_t chunk, uint32_t interleaved) {
+    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<1>];
+    load_operator<1>(Aops, sbuf);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, q = lane >> 4;
+    batch::sweep_items(prefix[ng], wave, kWavesPair, chunk, interleaved, [&](uint32_t it) {
+        const uint32_t g = batch::find_entry(prefix, ng, it);
+        const batch::ShotGrid& S = shots[ids[g]];
+        const uint32_t n = S.n, nbx = (n + 15) >> 4, local = it - prefix[g];
+        const uint32_t bx = local % nbx, rest = local / nbx, y = rest % n, z = 2 * (rest / n);
+        run_batch_pair_f32(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, y, z, z + 1 < n, lane, cl, q,
+                           (const float*)sbuf);
     });
 }
 
@@ -388,8 +384,8 @@ hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots,
                                     uint32_t chunk, uint32_t interleaved, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0 || chunk < 1) return hipErrorInvalidValue;
     if (precision == 1)
-        hipLaunchKernelGGL(fused_mixed_batch_kernel<1>, dim3(grid), dim3(kWaves * 64), 0, st, shots, ids, prefix, ng,
-                           (uint32_t)from, Aops, chunk, interleaved);
+        hipLaunchKernelGGL(fused_f32_pair_batch_kernel, dim3(grid), dim3(kWavesPair * 64), 0, st, shots, ids, prefix,
+                           ng, (uint32_t)from, Aops, chunk, interleaved);
     else if (precision == 2)
         hipLaunchKernelGGL(fused_mixed_batch_kernel<2>, dim3(grid), dim3(kWaves * 64), 0, st, shots, ids, prefix, ng,
                            (uint32_t)from, Aops, chunk, interleaved);
