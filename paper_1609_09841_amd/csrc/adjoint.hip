@@ -79,13 +79,17 @@ __global__ void inject_kernel(double* __restrict__ lam, const uint32_t* __restri
 // columns are the 128 (class p, class row r) pairs of lam (32 K-steps of 4,
 // step T holding class p = T / 4), the accumulators are the 8 parity groups
 // pi of the output columns c (16 columns each: 2 fields x 2x2x2 orders), and
-// group pi takes butterfly output p xor pi. Per batch of 16 nodes of one
-// x-row: 256 v_mfma_f64_16x16x4f64, the neighbour gathers and butterflies of
-// the forward half step, one store of each new value; no scratch.
+// group pi takes butterfly output p xor pi. The forward kernel's data flow
+// on the 4x4-tile instruction (v_mfma_f64_4x4x4f64, 4 blocks): per group and
+// K-step 4 row tiles, tile ri holding output rows (quarter i, register ri);
+// each wave computes two batches of 16 nodes, rows (y, z) and (y, z + 1),
+// which share every operator read and a plane of neighbours: the neighbours
+// s3 = 1 of the upper node are the neighbours s3 = 0 of the lower one, so a
+// step loads 12 values per lane instead of 16. Work comes from the
+// context's queue (fused::sweep_row_pairs); no scratch.
 // ---------------------------------------------------------------------------
-typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kMfWaves = 8;
-constexpr int kAdjOpDoubles = 8 * 32 * 64;  // [group][K-step][lane]
+constexpr int kAdjWaves = 4;                 // one wave per SIMD (two accumulator sets)
+constexpr int kAdjOpDoubles = 8 * 32 * 64;  // [K-step][group][row-tile pair][4k + i][2]
 constexpr int kAdjAhead = 2;
 constexpr int kAdjRing = kAdjAhead + 1;
 
@@ -137,41 +141,84 @@ __device__ __forceinline__ void adj_load_step(const double* __restrict__ lam, si
     for (int s = 0; s < 8; ++s) v[s] = b[c.corner[s]];
 }
 
+// Neighbours s = 0 .. 3 (the s3 = 0 plane) of a node, lam column of step T.
 template <int T>
-struct AdjSteps {
-    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t plane, const fused::Cell16& c,
-                                               const uint32_t* packed, int lane, const double* sK, d4* acc,
-                                               double (*ring)[8]) {
+__device__ __forceinline__ void adj_load_lower(const double* __restrict__ lam, size_t plane, const fused::Cell16& c,
+                                               const uint32_t* packed, double* v) {
+    const double* __restrict__ b = lam + (size_t)((packed[T >> 2] >> (8 * (T & 3))) & 0xFFu) * plane;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = b[c.corner[s]];
+}
+
+// ra: the lower node's 8 neighbour values; rb: the upper node's s3 = 0 four.
+template <int T>
+struct AdjStepsPair {
+    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t plane, const fused::Cell16& ca,
+                                               const fused::Cell16& cb, const uint32_t* packed, int lane,
+                                               const double* sK, double (*acca)[4], double (*accb)[4],
+                                               double (*ra)[8], double (*rb)[4]) {
         constexpr int p = T >> 2;  // class of this step's lam rows
-        if constexpr (T + kAdjAhead < 32)
-            adj_load_step<T + kAdjAhead>(lam, plane, c, packed, ring[(T + kAdjAhead) % kAdjRing]);
-        double U[8];
-        fused::butterfly8(ring[T % kAdjRing], U);
-        double a[8];
+        if constexpr (T + kAdjAhead < 32) {
+            adj_load_step<T + kAdjAhead>(lam, plane, ca, packed, ra[(T + kAdjAhead) % kAdjRing]);
+            adj_load_lower<T + kAdjAhead>(lam, plane, cb, packed, rb[(T + kAdjAhead) % kAdjRing]);
+        }
+        double Ua[8], Ub[8], vb[8];
 #pragma unroll
-        for (int pi = 0; pi < 8; ++pi) a[pi] = sK[(pi * 32 + T) * 64 + lane];
+        for (int s = 0; s < 4; ++s) vb[s] = rb[T % kAdjRing][s], vb[4 + s] = ra[T % kAdjRing][s];
+        fused::butterfly8(ra[T % kAdjRing], Ua);
+        fused::butterfly8(vb, Ub);
+        // this lane's A[i][k] (k = lane / 16, i = lane % 4) for row tiles
+        // 2 rp and 2 rp + 1 of group pi: one 16-byte read
+        const int at = ((lane >> 4) << 2) | (lane & 3);
+        const double2* __restrict__ sT = reinterpret_cast<const double2*>(sK) + (size_t)T * 8 * 2 * 16 + at;
+        double2 a[2][2];  // [group parity of the pipeline][rp]
 #pragma unroll
-        for (int pi = 0; pi < 8; ++pi) acc[pi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[pi], U[pi ^ p], acc[pi], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (T + 1 < 32) AdjSteps<T + 1>::run(lam, plane, c, packed, lane, sK, acc, ring);
+        for (int rp = 0; rp < 2; ++rp) a[0][rp] = sT[(0 * 2 + rp) * 16];
+#pragma unroll
+        for (int pi = 0; pi < 8; ++pi) {
+            if (pi + 1 < 8) {
+#pragma unroll
+                for (int rp = 0; rp < 2; ++rp) a[(pi + 1) & 1][rp] = sT[((pi + 1) * 2 + rp) * 16];
+            }
+#pragma unroll
+            for (int ri = 0; ri < 4; ++ri) {
+                const double2 av = a[pi & 1][ri >> 1];
+                const double x = (ri & 1) ? av.y : av.x;
+                acca[pi][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64(x, Ua[pi ^ p], acca[pi][ri], 0, 0, 0);
+                accb[pi][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64(x, Ub[pi ^ p], accb[pi][ri], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (T + 1 < 32) AdjStepsPair<T + 1>::run(lam, plane, ca, cb, packed, lane, sK, acca, accb, ra, rb);
     }
 };
 
 template <int T>
-struct AdjPrologue {
-    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t plane, const fused::Cell16& c,
-                                               const uint32_t* packed, double (*ring)[8]) {
-        adj_load_step<T>(lam, plane, c, packed, ring[T]);
-        if constexpr (T + 1 < kAdjAhead) AdjPrologue<T + 1>::run(lam, plane, c, packed, ring);
+struct AdjProloguePair {
+    __device__ __forceinline__ static void run(const double* __restrict__ lam, size_t plane, const fused::Cell16& ca,
+                                               const fused::Cell16& cb, const uint32_t* packed, double (*ra)[8],
+                                               double (*rb)[4]) {
+        adj_load_step<T>(lam, plane, ca, packed, ra[T]);
+        adj_load_lower<T>(lam, plane, cb, packed, rb[T]);
+        if constexpr (T + 1 < kAdjAhead) AdjProloguePair<T + 1>::run(lam, plane, ca, cb, packed, ra, rb);
     }
 };
 
-// Persistent kernel over the XCD-blocked row sweep (fused::sweep_rows), one
-// batch of 16 consecutive nodes per wave and step of the sweep.
-__global__ __launch_bounds__(kMfWaves * 64) void adjoint_mfma_kernel(const double* __restrict__ lam_dst,
-                                                                     double* __restrict__ lam_src,
-                                                                     const double* __restrict__ KT, uint32_t n,
-                                                                     size_t pitch, uint32_t off) {
+__device__ __forceinline__ void adj_store(double* __restrict__ lam_src, size_t pitch, uint32_t node, int q,
+                                          const double (*acc)[4]) {
+#pragma unroll
+    for (int pi = 0; pi < 8; ++pi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lam_src[(size_t)adj_out_col(pi, q, r) * pitch + node] = acc[pi][r];
+}
+
+// Persistent kernel over the queue-fed row-pair sweep: one pair of 16-node
+// batches per wave and item, nodes x0 .. x0+15 of rows (y, z) and (y, z + 1)
+// (periodic; the second stored only if upper is set).
+__global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void adjoint_mfma_kernel(const double* __restrict__ lam_dst, double* __restrict__ lam_src,
+                         const double* __restrict__ KT, uint32_t n, size_t pitch, uint32_t off,
+                         uint32_t* __restrict__ queue) {
     __shared__ double sK[kAdjOpDoubles];
     for (int i = threadIdx.x; i < kAdjOpDoubles; i += blockDim.x) sK[i] = KT[i];
     __syncthreads();
@@ -180,26 +227,27 @@ __global__ __launch_bounds__(kMfWaves * 64) void adjoint_mfma_kernel(const doubl
     uint32_t packed[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) packed[k] = kAdjColTable.w[q][k];
-    fused::sweep_rows(n, wave, kMfWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
+    fused::sweep_row_pairs(n, wave, kAdjWaves, queue, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
         const uint32_t x = x0 + cl;
         const bool valid = x < n;
-        const uint32_t node = (z * n + y) * n + (valid ? x : n - 1);
-        const fused::Cell16 c = node_neighbours(node, n, off);
-        // opaque per batch (keeps the per-lane column bases from being hoisted
+        const uint32_t xx = valid ? x : n - 1, zb = (z + 1 == n) ? 0 : z + 1;
+        const uint32_t na = (z * n + y) * n + xx, nb = (zb * n + y) * n + xx;
+        const fused::Cell16 ca = node_neighbours(na, n, off);
+        const fused::Cell16 cb = node_neighbours(nb, n, off);
+        // opaque per item (keeps the per-lane column bases from being hoisted
         // out of the sweep, which would pin 64 registers)
 #pragma unroll
         for (int w = 0; w < 8; ++w) asm volatile("" : "+v"(packed[w]));
-        d4 acc[8];
-#pragma unroll
-        for (int pi = 0; pi < 8; ++pi) acc[pi] = d4{0.0, 0.0, 0.0, 0.0};
-        double ring[kAdjRing][8];
-        AdjPrologue<0>::run(lam_dst, pitch, c, packed, ring);
-        AdjSteps<0>::run(lam_dst, pitch, c, packed, lane, sK, acc, ring);
-        if (!valid) return;
+        double acca[8][4], accb[8][4];
 #pragma unroll
         for (int pi = 0; pi < 8; ++pi)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lam_src[(size_t)adj_out_col(pi, q, r) * pitch + node] = acc[pi][r];
+            for (int r = 0; r < 4; ++r) acca[pi][r] = accb[pi][r] = 0.0;
+        double ra[kAdjRing][8], rb[kAdjRing][4];
+        AdjProloguePair<0>::run(lam_dst, pitch, ca, cb, packed, ra, rb);
+        AdjStepsPair<0>::run(lam_dst, pitch, ca, cb, packed, lane, sK, acca, accb, ra, rb);
+        if (valid) adj_store(lam_src, pitch, na, q, acca);
+        if (valid && upper) adj_store(lam_src, pitch, nb, q, accb);
     });
 }
 
@@ -280,24 +328,24 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(const double* __restr
 size_t adjoint_mfma_operator_doubles() { return (size_t)kAdjOpDoubles; }
 
 void adjoint_mfma_build_operator(const double* K, double* KT) {
-    // K: canonical [8][16][128]. A operand of (group pi, step T): lane = i + 16 k,
-    // A[i][k] = K_p[4 (T % 4) + k][column of logical row 4 (i % 4) + i / 4 of
-    // group pi], p = T / 4: the MFMA leaves output row i in register i / 4 of
-    // lane quarter i % 4, so register r of quarter g holds logical row 4 g + r.
-    for (int pi = 0; pi < 8; ++pi)
-        for (int T = 0; T < 32; ++T)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int i = lane & 15, k = lane >> 4, p = T >> 2;
-                KT[((size_t)pi * 32 + T) * 64 + lane] =
-                    K[((size_t)p * 16 + 4 * (T & 3) + k) * 128 + adj_out_col(pi, i & 3, i >> 2)];
-            }
+    // K: canonical [8][16][128]. Row tile ri of group pi at step T (p = T / 4):
+    // A[i][k] = K_p[4 (T % 4) + k][column of the output row held in register ri
+    // of lane quarter i], stored at ((((T 8 + pi) 2 + ri / 2) 16 + 4 k + i) 2 +
+    // ri % 2: a lane reads the two tiles of a row-tile pair as one 16-byte value.
+    for (int T = 0; T < 32; ++T)
+        for (int pi = 0; pi < 8; ++pi)
+            for (int ri = 0; ri < 4; ++ri)
+                for (int k = 0; k < 4; ++k)
+                    for (int i = 0; i < 4; ++i)
+                        KT[((((size_t)T * 8 + pi) * 2 + (ri >> 1)) * 16 + 4 * k + i) * 2 + (ri & 1)] =
+                            K[((size_t)(T >> 2) * 16 + 4 * (T & 3) + k) * 128 + adj_out_col(pi, i, ri)];
 }
 
 hipError_t launch_adjoint_mfma(const double* lam_dst, double* lam_src, const double* KT, int n, size_t pitch, int off,
-                               int grid, hipStream_t st) {
-    if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(adjoint_mfma_kernel, dim3(grid), dim3(kMfWaves * 64), 0, st, lam_dst, lam_src, KT,
-                       (uint32_t)n, pitch, (uint32_t)off);
+                               int grid, uint32_t* queue, hipStream_t st) {
+    if (grid < 8 || grid % 8 != 0 || queue == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(adjoint_mfma_kernel, dim3(grid), dim3(kAdjWaves * 64), 0, st, lam_dst, lam_src, KT,
+                       (uint32_t)n, pitch, (uint32_t)off, queue);
     return hipGetLastError();
 }
 

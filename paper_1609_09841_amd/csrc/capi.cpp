@@ -515,7 +515,7 @@ hipError_t adjoint_half(hermite_ctx* ctx, const double* lam_dst, double* lam_src
     if (ctx->m == 3) {
         const int grid = ctx->cus >= 8 ? (ctx->cus / 8) * 8 : 8;
         return hermite::launch_adjoint_mfma(lam_dst, lam_src, (const double*)ctx->Kadj, ctx->n, ctx->pitch,
-                                            off, grid, ctx->stream);
+                                            off, grid, ctx->queue, ctx->stream);
     }
     return hermite::launch_adjoint(ctx->m, lam_dst, lam_src, (const double*)ctx->Kadj, ctx->n, ctx->pitch, off,
                                    ctx->stream);
@@ -548,6 +548,13 @@ int hermite_adjoint_init(hermite_ctx* ctx, const void* lam_u_dev, const void* la
         HCHECK(ctx, hipMalloc(&ctx->Kadj, K.size() * sizeof(double)), "hipMalloc(adjoint operator)");
         HCHECK(ctx, hipMemcpy(ctx->Kadj, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice),
                "upload adjoint operator");
+    }
+    if (ctx->m == 3 && !ctx->queue) {
+        // the m = 3 transposed half step takes its work from the context's queue
+        const std::vector<uint32_t> zero(hermite::kMfma4QueueWords, 0u);
+        HCHECK(ctx, hipMalloc(&ctx->queue, zero.size() * sizeof(uint32_t)), "hipMalloc(queue)");
+        HCHECK(ctx, hipMemcpy(ctx->queue, zero.data(), zero.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+               "clear queue");
     }
     const size_t rows = (size_t)ctx->M3, w = ctx->ncell * sizeof(double), dp = ctx->pitch * sizeof(double);
     double* g = ctx->grid[0];

@@ -116,10 +116,11 @@ hipError_t launch_source_dot(const SourceDesc* src, const uint32_t* prefix, uint
 hipError_t launch_adjoint(int m, const double* lam_dst, double* lam_src, const double* K, int n, size_t pitch, int off,
                           hipStream_t st);
 // m = 3 on the matrix cores: KT = adjoint_mfma_build_operator(K)
-// (adjoint_mfma_operator_doubles() doubles); grid as for launch_fused_mfma.
-// One launch, no scratch.
+// (adjoint_mfma_operator_doubles() doubles); grid as for launch_fused_mfma,
+// queue as for launch_fused_mfma4 (the context's own). One launch, no
+// scratch.
 hipError_t launch_adjoint_mfma(const double* lam_dst, double* lam_src, const double* KT, int n, size_t pitch, int off,
-                               int grid, hipStream_t st);
+                               int grid, uint32_t* queue, hipStream_t st);
 size_t adjoint_mfma_operator_doubles();
 void adjoint_mfma_build_operator(const double* K, double* KT);
 // Receivers: traces[r] = grid[nodes[r]] (u, d = 0 of the primal grid);
