@@ -358,11 +358,11 @@ int hermite_batch_create(int n_shots, const hermite_shot* shots, double cfl, dou
             std::vector<uint32_t> pre(1, 0);
             for (uint32_t s : g.ids) {
                 const uint64_t n = shots[s].n_cells;
-                // m = 3: 16-cell batches of a z-adjacent row pair (FP64,
-                // FP32) or of one row (BF16x3) per work item
+                // m = 3: the 16-cell batches of a z-adjacent row pair per
+                // work item, in every precision (the kernels decode item
+                // numbers below n ceil(n/2) ceil(n/16) only)
                 const uint64_t items = (m < 3) ? (n * n * n + kSmallBlocks[cnd] - 1) / kSmallBlocks[cnd]
-                                       : (o.precision != HERMITE_PREC_BF16X3) ? n * ((n + 1) / 2) * ((n + 15) / 16)
-                                                                              : n * n * ((n + 15) / 16);
+                                               : n * ((n + 1) / 2) * ((n + 15) / 16);
                 if (pre.back() + items > 0xFFFFFFFFull)
                     return bail(bfail(b, HERMITE_EINVAL, "order-%d shots exceed 2^32 work items", m));
                 pre.push_back(pre.back() + (uint32_t)items);

@@ -300,8 +300,7 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         e = hipMemcpy(ctx->K, Kdev.data(), Kdev.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "upload K"));
     }
-    if (nf == 2 && m == 3 && o.fused &&
-        ((o.precision == HERMITE_PREC_FP64 && ctx->m3_kernel == 2) || o.precision == HERMITE_PREC_FP32)) {
+    if (nf == 2 && m == 3 && o.fused && (o.precision != HERMITE_PREC_FP64 || ctx->m3_kernel == 2)) {
         // the context's own work queue: contexts on different streams may run at once
         const std::vector<uint32_t> zero(hermite::kMfma4QueueWords, 0u);
         e = hipMalloc(&ctx->queue, zero.size() * sizeof(uint32_t));

@@ -15,14 +15,14 @@
 //
 // FP32: v_mfma_f32_16x16x4f32, one K-step per input column chunk, the same
 // shape as the FP64 kernel (A = operator rows x 4 columns, B = 4 columns x 16
-// cells; register r of lane quarter q holds row 4q + r). A single grid runs
-// two z-adjacent batches per wave (StepsF32Pair), on a single grid and in
-// batches of shots.
+// cells; register r of lane quarter q holds row 4q + r).
 // BF16x3: v_mfma_f32_16x16x16_bf16 over 8 K-steps of 16 columns (lane
 // quarter q supplies k = 4q .. 4q+3). Operator and inputs are split into a
 // high and a low BF16 part (x = x_hi + x_lo, each round-to-nearest-even) and
 // the three products lo*hi, hi*lo, hi*hi are accumulated in FP32; the lo*lo
 // term is dropped (relative weight 2^-16 and below).
+// Both run two z-adjacent batches per wave (StepsF32Pair, StepsBf16Pair), on
+// a single grid and in batches of shots.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -43,13 +43,6 @@ using fused::OwnSchedule;
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));  // 4 BF16 bit patterns
 
-constexpr int kWaves = 8;
-// software-pipeline depth (steps whose corner loads are in flight) per
-// precision: the BF16 path keeps two split input buffers live and has
-// registers for one step ahead only
-template <int PREC>
-constexpr int kAhead = (PREC == 1) ? 2 : 1;
-constexpr int kRing = 3;
 constexpr int kF32Floats = 8 * 32 * 64;      // [class][step][lane]
 constexpr int kBf16Vecs = 8 * 8 * 2 * 64;    // [class][K-step][hi/lo][lane] of 4 BF16
 
@@ -61,15 +54,6 @@ __device__ __forceinline__ void load_own(const double* __restrict__ base, size_t
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = b[c.corner[s]];
 }
-
-template <int AH, int T>
-struct Prologue {
-    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& c,
-                                               double (*ring)[8]) {
-        load_own<T>(base, pitch, c, ring[T]);
-        if constexpr (T + 1 < AH) Prologue<AH, T + 1>::run(base, pitch, c, ring);
-    }
-};
 
 // ---------------------------------------------------------------- FP32
 // Two batches per wave, the cells (x, y, z) and (x, y, z + 1), as in the FP64
@@ -135,38 +119,68 @@ struct StepsF32Pair {
 };
 
 // ---------------------------------------------------------------- BF16x3
+// BF16x3, two z-adjacent batches per wave (as StepsF32Pair): the split
+// operator tiles read from LDS feed both batches' three products.
+constexpr int kAheadBf16Pair = 3;
+constexpr int kRingBf16Pair = kAheadBf16Pair + 1;
+
 template <int T>
-struct StepsBf16 {
-    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& c,
-                                               int lane, const s4* sA, f4* acc, double (*P0)[4],
-                                               double (*ring)[8], s4* Bhi, s4* Blo) {
+struct PrologueBf16Pair {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& ca,
+                                               const Cell16& cb, double (*ra)[8], double (*rb)[4]) {
+        load_own<T>(base, pitch, ca, ra[T]);
+        load_own_upper<T>(base, pitch, cb, rb[T]);
+        if constexpr (T + 1 < kAheadBf16Pair) PrologueBf16Pair<T + 1>::run(base, pitch, ca, cb, ra, rb);
+    }
+};
+
+template <int T>
+struct StepsBf16Pair {
+    __device__ __forceinline__ static void run(const double* __restrict__ base, size_t pitch, const Cell16& ca,
+                                               const Cell16& cb, int lane, const s4* sA, f4* acca, f4* accb,
+                                               double (*P0a)[4], double (*P0b)[4], double (*ra)[8], double (*rb)[4],
+                                               s4* Bhia, s4* Bloa, s4* Bhib, s4* Blob) {
         constexpr OwnSchedule S{};
         constexpr int u = S.u[T], dp = OwnSchedule::parity(u), rg = OwnSchedule::reg(u);
         constexpr int ks = T / 4, e = T % 4;
-        constexpr int AH = kAhead<2>;
-        if constexpr (T + AH < 32) load_own<T + AH>(base, pitch, c, ring[(T + AH) % kRing]);
-        double Tv[8];
-        butterfly8(ring[T % kRing], Tv);
-        P0[dp][rg] = 0.125 * Tv[0];
+        constexpr int AH = kAheadBf16Pair, R = kRingBf16Pair;
+        if constexpr (T + AH < 32) {
+            load_own<T + AH>(base, pitch, ca, ra[(T + AH) % R]);
+            load_own_upper<T + AH>(base, pitch, cb, rb[(T + AH) % R]);
+        }
+        double Ta[8], Tb[8], vb[8];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) vb[s] = ra[T % R][4 + s], vb[4 + s] = rb[T % R][s];
+        butterfly8(ra[T % R], Ta);
+        butterfly8(vb, Tb);
+        P0a[dp][rg] = 0.125 * Ta[0];
+        P0b[dp][rg] = 0.125 * Tb[0];
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const float x = (float)Tv[p ^ dp];
-            const __bf16 hi = (__bf16)x;  // round to nearest even
-            Bhi[p][e] = __builtin_bit_cast(short, hi);
-            Blo[p][e] = __builtin_bit_cast(short, (__bf16)(x - (float)hi));
+            const float xa = (float)Ta[p ^ dp], xb = (float)Tb[p ^ dp];
+            const __bf16 ha = (__bf16)xa, hb = (__bf16)xb;  // round to nearest even
+            Bhia[p][e] = __builtin_bit_cast(short, ha);
+            Bloa[p][e] = __builtin_bit_cast(short, (__bf16)(xa - (float)ha));
+            Bhib[p][e] = __builtin_bit_cast(short, hb);
+            Blob[p][e] = __builtin_bit_cast(short, (__bf16)(xb - (float)hb));
         }
         if constexpr (e == 3) {
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
                 const s4 ahi = sA[((p * 8 + ks) * 2 + 0) * 64 + lane];
                 const s4 alo = sA[((p * 8 + ks) * 2 + 1) * 64 + lane];
-                acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, Bhi[p], acc[p], 0, 0, 0);
-                acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Blo[p], acc[p], 0, 0, 0);
-                acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Bhi[p], acc[p], 0, 0, 0);
+                acca[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, Bhia[p], acca[p], 0, 0, 0);
+                accb[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, Bhib[p], accb[p], 0, 0, 0);
+                acca[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Bloa[p], acca[p], 0, 0, 0);
+                accb[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Blob[p], accb[p], 0, 0, 0);
+                acca[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Bhia[p], acca[p], 0, 0, 0);
+                accb[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, Bhib[p], accb[p], 0, 0, 0);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (T + 1 < 32) StepsBf16<T + 1>::run(base, pitch, c, lane, sA, acc, P0, ring, Bhi, Blo);
+        if constexpr (T + 1 < 32)
+            StepsBf16Pair<T + 1>::run(base, pitch, ca, cb, lane, sA, acca, accb, P0a, P0b, ra, rb, Bhia, Bloa, Bhib,
+                                      Blob);
     }
 };
 
@@ -187,40 +201,13 @@ __device__ __forceinline__ void store_batch(double* __restrict__ dst, size_t pla
     }
 }
 
-// One batch: the 16 neighbouring cells of row (y, z) whose new nodes are
-// x0 .. x0+15 (lower corners x0 - off .., periodic); lanes past the end of
-// the row compute a copy of the last cell and store nothing.
+// The batch of row (y, z) and the one above it, row (y, z + 1) (periodic),
+// stored only if upper is set; PREC 1 = FP32, 2 = BF16x3.
 template <int PREC>
-__device__ __forceinline__ void run_batch(const double* __restrict__ src, double* __restrict__ dst, size_t pitch,
-                                          uint32_t n, uint32_t off, uint32_t x0, uint32_t y, uint32_t z, int lane,
-                                          int cl, int q, const unsigned char* sbuf) {
-    const uint32_t x = x0 + cl;
-    const bool valid = x < n;
-    // lane cl produces new node x0 + cl of row (y + off, z + off): the cell's
-    // lower corner is x - off, so that the stores of a batch fill whole
-    // 128-byte lines also in the dual -> primal half step
-    const Cell16 c = cell_nodes((z * n + y) * n + (valid ? (x + n - off) % n : n - 1), n, off);
-    const double* base = src + (size_t)(32 * q) * pitch;
-    // opaque per batch, so per-step addresses are not hoisted out of the sweep
-    asm volatile("" : "+v"(base));
-    f4 acc[8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
-    double P0[8][4];
-    double ring[kRing][8];
-    Prologue<kAhead<PREC>, 0>::run(base, pitch, c, ring);
-    static_assert(PREC == 2, "FP32 runs batch pairs (run_batch_pair_f32)");
-    s4 Bhi[8], Blo[8];
-    StepsBf16<0>::run(base, pitch, c, lane, (const s4*)sbuf, acc, P0, ring, Bhi, Blo);
-    if (valid) store_batch(dst, pitch, c, q, acc, P0);
-}
-
-// FP32: the batch of row (y, z) and the one above it, row (y, z + 1)
-// (periodic), stored only if upper is set.
-__device__ __forceinline__ void run_batch_pair_f32(const double* __restrict__ src, double* __restrict__ dst,
-                                                   size_t pitch, uint32_t n, uint32_t off, uint32_t x0, uint32_t y,
-                                                   uint32_t z, bool upper, int lane, int cl, int q,
-                                                   const float* sA) {
+__device__ __forceinline__ void run_batch_pair_mixed(const double* __restrict__ src, double* __restrict__ dst,
+                                                     size_t pitch, uint32_t n, uint32_t off, uint32_t x0, uint32_t y,
+                                                     uint32_t z, bool upper, int lane, int cl, int q,
+                                                     const unsigned char* sbuf) {
     const uint32_t x = x0 + cl;
     const bool valid = x < n;
     const uint32_t cx = valid ? (x + n - off) % n : n - 1;
@@ -233,9 +220,17 @@ __device__ __forceinline__ void run_batch_pair_f32(const double* __restrict__ sr
 #pragma unroll
     for (int p = 0; p < 8; ++p) acca[p] = accb[p] = f4{0.f, 0.f, 0.f, 0.f};
     double P0a[8][4], P0b[8][4];
-    double ra[kRingPair][8], rb[kRingPair][4];
-    PrologueF32Pair<0>::run(base, pitch, ca, cb, ra, rb);
-    StepsF32Pair<0>::run(base, pitch, ca, cb, lane, sA, acca, accb, P0a, P0b, ra, rb);
+    if constexpr (PREC == 1) {
+        double ra[kRingPair][8], rb[kRingPair][4];
+        PrologueF32Pair<0>::run(base, pitch, ca, cb, ra, rb);
+        StepsF32Pair<0>::run(base, pitch, ca, cb, lane, (const float*)sbuf, acca, accb, P0a, P0b, ra, rb);
+    } else {
+        double ra[kRingBf16Pair][8], rb[kRingBf16Pair][4];
+        s4 Bhia[8], Bloa[8], Bhib[8], Blob[8];
+        PrologueBf16Pair<0>::run(base, pitch, ca, cb, ra, rb);
+        StepsBf16Pair<0>::run(base, pitch, ca, cb, lane, (const s4*)sbuf, acca, accb, P0a, P0b, ra, rb, Bhia, Bloa,
+                              Bhib, Blob);
+    }
     if (valid) store_batch(dst, pitch, ca, q, acca, P0a);
     if (valid && upper) store_batch(dst, pitch, cb, q, accb, P0b);
 }
@@ -252,47 +247,35 @@ __device__ __forceinline__ void load_operator(const void* __restrict__ Aops, uns
 template <int PREC>
 constexpr int kOpBytes = (PREC == 1) ? kF32Floats * 4 : kBf16Vecs * 8;
 
-template <int PREC>  // 1 = FP32, 2 = BF16x3
-__global__ __launch_bounds__(kWaves * 64) void fused_mixed_kernel(const double* __restrict__ src,
-                                                                  double* __restrict__ dst,
-                                                                  const void* __restrict__ Aops, uint32_t n,
-                                                                  size_t pitch, uint32_t off) {
+// A single grid in FP32 (PREC 1) or BF16x3 (PREC 2): two z-adjacent batches
+// per wave over the queue-fed row-pair sweep (fused::sweep_row_pairs). The
+// second set of accumulators and P0 values takes the registers of a second
+// wave: one wave per SIMD, four per workgroup.
+constexpr int kWavesPair = 4;
+
+template <int PREC>
+__global__ __launch_bounds__(kWavesPair * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_mixed_pair_kernel(const double* __restrict__ src, double* __restrict__ dst, const void* __restrict__ Aops,
+                             uint32_t n, size_t pitch, uint32_t off, uint32_t* __restrict__ queue) {
     __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<PREC>];
     load_operator<PREC>(Aops, sbuf);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
-    fused::sweep_rows(n, wave, kWaves, [&](uint32_t x0, uint32_t y, uint32_t z) {
-        run_batch<PREC>(src, dst, pitch, n, off, x0, y, z, lane, cl, q, sbuf);
-    });
-}
-
-// FP32 on a single grid: two z-adjacent batches per wave (StepsF32Pair) over
-// the queue-fed row-pair sweep (fused::sweep_row_pairs). The second set of
-// accumulators and P0 values takes the registers of a second wave: one wave
-// per SIMD, four per workgroup.
-constexpr int kWavesPair = 4;
-
-__global__ __launch_bounds__(kWavesPair * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void fused_f32_pair_kernel(const double* __restrict__ src, double* __restrict__ dst, const void* __restrict__ Aops,
-                           uint32_t n, size_t pitch, uint32_t off, uint32_t* __restrict__ queue) {
-    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<1>];
-    load_operator<1>(Aops, sbuf);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int cl = lane & 15, q = lane >> 4;
     fused::sweep_row_pairs(n, wave, kWavesPair, queue, [&](uint32_t x0, uint32_t y, uint32_t z, bool upper) {
-        run_batch_pair_f32(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q, (const float*)sbuf);
+        run_batch_pair_mixed<PREC>(src, dst, pitch, n, off, x0, y, z, upper, lane, cl, q, sbuf);
     });
 }
 
-// FP32 batches of shots: item (bx, y, zp) of a shot, bx fastest, is the pair
-// of rows (y, 2 zp) and (y, 2 zp + 1) at x-batch bx (n ceil(n/2) ceil(n/16)
+// Batches of shots: item (bx, y, zp) of a shot, bx fastest, is the pair of
+// rows (y, 2 zp) and (y, 2 zp + 1) at x-batch bx (n ceil(n/2) ceil(n/16)
 // items per shot, the FP64 batch kernel's numbering).
+template <int PREC>
 __global__ __launch_bounds__(kWavesPair * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void fused_f32_pair_batch_kernel(const batch::ShotGrid* __restrict__ shots, const uint32_t* __restrict__ ids,
-                                 const uint32_t* __restrict__ prefix, uint32_t ng, uint32_t from,
-                                 const void* __restrict__ Aops, uint32_t chunk, uint32_t interleaved) {
-    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<1>];
-    load_operator<1>(Aops, sbuf);
+void fused_mixed_pair_batch_kernel(const batch::ShotGrid* __restrict__ shots, const uint32_t* __restrict__ ids,
+                                   const uint32_t* __restrict__ prefix, uint32_t ng, uint32_t from,
+                                   const void* __restrict__ Aops, uint32_t chunk, uint32_t interleaved) {
+    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<PREC>];
+    load_operator<PREC>(Aops, sbuf);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane & 15, q = lane >> 4;
     batch::sweep_items(prefix[ng], wave, kWavesPair, chunk, interleaved, [&](uint32_t it) {
@@ -300,30 +283,8 @@ void fused_f32_pair_batch_kernel(const batch::ShotGrid* __restrict__ shots, cons
         const batch::ShotGrid& S = shots[ids[g]];
         const uint32_t n = S.n, nbx = (n + 15) >> 4, local = it - prefix[g];
         const uint32_t bx = local % nbx, rest = local / nbx, y = rest % n, z = 2 * (rest / n);
-        run_batch_pair_f32(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, y, z, z + 1 < n, lane, cl, q,
-                           (const float*)sbuf);
-    });
-}
-
-// Batched: the 16-cell batches of every shot of the group (batch_common.h).
-template <int PREC>
-__global__ __launch_bounds__(kWaves * 64) void fused_mixed_batch_kernel(const batch::ShotGrid* __restrict__ shots,
-                                                                        const uint32_t* __restrict__ ids,
-                                                                        const uint32_t* __restrict__ prefix,
-                                                                        uint32_t ng, uint32_t from,
-                                                                        const void* __restrict__ Aops,
-                                                                        uint32_t chunk, uint32_t interleaved) {
-    __shared__ __attribute__((aligned(16))) unsigned char sbuf[kOpBytes<PREC>];
-    load_operator<PREC>(Aops, sbuf);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int cl = lane & 15, q = lane >> 4;
-    batch::sweep_items(prefix[ng], wave, kWaves, chunk, interleaved, [&](uint32_t it) {
-        const uint32_t g = batch::find_entry(prefix, ng, it);
-        const batch::ShotGrid& S = shots[ids[g]];
-        const uint32_t n = S.n, nbx = (n + 15) >> 4, local = it - prefix[g];
-        const uint32_t bx = local % nbx, row = local / nbx;
-        run_batch<PREC>(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, row % n, row / n, lane, cl, q,
-                        sbuf);
+        run_batch_pair_mixed<PREC>(S.grid[from], S.grid[1 - from], S.pitch, n, from, bx * 16, y, z, z + 1 < n, lane,
+                                   cl, q, sbuf);
     });
 }
 
@@ -384,11 +345,11 @@ hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots,
                                     uint32_t chunk, uint32_t interleaved, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0 || chunk < 1) return hipErrorInvalidValue;
     if (precision == 1)
-        hipLaunchKernelGGL(fused_f32_pair_batch_kernel, dim3(grid), dim3(kWavesPair * 64), 0, st, shots, ids, prefix,
-                           ng, (uint32_t)from, Aops, chunk, interleaved);
+        hipLaunchKernelGGL(fused_mixed_pair_batch_kernel<1>, dim3(grid), dim3(kWavesPair * 64), 0, st, shots, ids,
+                           prefix, ng, (uint32_t)from, Aops, chunk, interleaved);
     else if (precision == 2)
-        hipLaunchKernelGGL(fused_mixed_batch_kernel<2>, dim3(grid), dim3(kWaves * 64), 0, st, shots, ids, prefix, ng,
-                           (uint32_t)from, Aops, chunk, interleaved);
+        hipLaunchKernelGGL(fused_mixed_pair_batch_kernel<2>, dim3(grid), dim3(kWavesPair * 64), 0, st, shots, ids,
+                           prefix, ng, (uint32_t)from, Aops, chunk, interleaved);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -397,13 +358,13 @@ hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots,
 hipError_t launch_fused_mixed(int precision, const double* src, double* dst, const void* Aops, int n, size_t pitch,
                               int off, int grid, uint32_t* queue, hipStream_t st) {
     if (grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
-    if (precision == 1 && queue == nullptr) return hipErrorInvalidValue;
+    if (queue == nullptr) return hipErrorInvalidValue;
     if (precision == 1)
-        hipLaunchKernelGGL(fused_f32_pair_kernel, dim3(grid), dim3(kWavesPair * 64), 0, st, src, dst, Aops,
+        hipLaunchKernelGGL(fused_mixed_pair_kernel<1>, dim3(grid), dim3(kWavesPair * 64), 0, st, src, dst, Aops,
                            (uint32_t)n, pitch, (uint32_t)off, queue);
     else if (precision == 2)
-        hipLaunchKernelGGL(fused_mixed_kernel<2>, dim3(grid), dim3(kWaves * 64), 0, st, src, dst, Aops, (uint32_t)n,
-                           pitch, (uint32_t)off);
+        hipLaunchKernelGGL(fused_mixed_pair_kernel<2>, dim3(grid), dim3(kWavesPair * 64), 0, st, src, dst, Aops,
+                           (uint32_t)n, pitch, (uint32_t)off, queue);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

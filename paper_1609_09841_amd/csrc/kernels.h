@@ -149,8 +149,8 @@ hipError_t launch_fused_valu_small_batch(int m, int block, const batch::ShotGrid
 hipError_t launch_fused_mfma_batch(const batch::ShotGrid* shots, const uint32_t* ids, const uint32_t* prefix,
                                    uint32_t ng, int from, const double* K4, int grid, uint32_t chunk,
                                    uint32_t interleaved, hipStream_t st);
-// FP32 works on z-adjacent row pairs (items counted as for
-// launch_fused_mfma_batch), BF16x3 on single rows (n n ceil(n/16) items).
+// Both precisions work on z-adjacent row pairs (items counted as for
+// launch_fused_mfma_batch).
 hipError_t launch_fused_mixed_batch(int precision, const batch::ShotGrid* shots, const uint32_t* ids,
                                     const uint32_t* prefix, uint32_t ng, int from, const void* Aops, int grid,
                                     uint32_t chunk, uint32_t interleaved, hipStream_t st);
