@@ -231,3 +231,29 @@ def test_differentiation_workload_small_copy():
     rhs = np.sum(xs[0] * gu.cpu().numpy()) + np.sum(xs[1] * gut.cpu().numpy())
     scale = np.sqrt(np.sum(fu ** 2) + np.sum(fut ** 2)) * np.sqrt(np.sum(y[0] ** 2) + np.sum(y[1] ** 2))
     assert abs(lhs - rhs) / scale <= 1e-13
+
+
+@pytest.mark.parametrize("kernel", ["mfma", "valu"])
+def test_m3_adjoint_on_contexts_of_other_forward_kernels(kernel):
+    """A context whose forward half step is not the default kernel has no
+    work queue until the adjoint needs one: its transposed half steps equal
+    those of a default context bit for bit (odd n, so the last row pair of
+    some XCDs has no upper row)."""
+    n, steps, M = 21, 3, 4
+    rng = np.random.default_rng(2100)
+    x = [rng.standard_normal((M, M, M, n, n, n)) for _ in range(2)]
+    y = [rng.standard_normal((M, M, M, n, n, n)) for _ in range(2)]
+    print(f"[adjoint queue] n={n} kernel={kernel}", flush=True)
+    out = {}
+    for kern in ("auto", kernel):
+        with B.Solver(n, 3, 0.5, 1.0, kernel=kern) as s:
+            s.set_initial(*x)
+            s.step(steps)
+            gu = torch.empty((M, M, M, n, n, n), dtype=torch.float64, device="cuda")
+            gut = torch.empty_like(gu)
+            s.adjoint_init(_t(y[0]), _t(y[1]))
+            s.adjoint_step(steps)
+            s.adjoint_gather(gu, gut)
+            s.sync()
+            out[kern] = (gu.cpu().numpy(), gut.cpu().numpy())
+    assert np.array_equal(out["auto"][0], out[kernel][0]) and np.array_equal(out["auto"][1], out[kernel][1])
