@@ -383,7 +383,8 @@ int hermite_batch_create(int n_shots, const hermite_shot* shots, double cfl, dou
             hermite::mixed_build_operators(o.precision, K.data(), Kdev.data());
         } else {
             Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
-            hermite::mfma4_arrange_operators(K.data(), (double*)Kdev.data());
+            if (!hermite::mfma4_arrange_operators(K.data(), (double*)Kdev.data()))
+                return bail(bfail(b, HERMITE_EUNSUPPORTED, "class operator has a nonzero entry the kernel skips"));
         }
         if ((rc = upload(b, (unsigned char**)&g.K, Kdev, "upload operator")) != HERMITE_OK) return bail(rc);
     }

@@ -285,7 +285,8 @@ int hermite_create(int n_cells, int m, double cfl, double c, const hermite_optio
         hermite::mfma_permute_operators(K.data(), (double*)Kdev.data());
     } else if (m == 3 && o.fused && ctx->m3_kernel == 2) {
         Kdev.resize(hermite::mfma_operator_doubles() * sizeof(double));
-        hermite::mfma4_arrange_operators(K.data(), (double*)Kdev.data());
+        if (!hermite::mfma4_arrange_operators(K.data(), (double*)Kdev.data()))
+            return bail(fail(ctx, HERMITE_EUNSUPPORTED, "class operator has a nonzero entry the kernel skips"));
     } else if (m == 3) {
         Kdev.resize(hermite::valu4_operator_doubles() * sizeof(double));
         hermite::valu4_build_operators(K.data(), (double*)Kdev.data());

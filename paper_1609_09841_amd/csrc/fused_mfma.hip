@@ -108,6 +108,36 @@ struct Steps {
 constexpr int kAhead4 = 2;
 constexpr int kRing4 = kAhead4 + 1;
 
+// Row tiles that are zero for every operator: entry (row, column) of class p
+// vanishes whenever on some axis x the class parity p_x is 0, the output's
+// o_x is 1 and the input's d_x is 0 (the even part of the 1D interpolant has
+// no second-order term from the values, and the evolution lowers orders in
+// steps of two). Tile ri of class p at step T holds rows 4 i + ri (i = field
+// and o3, ri = o2 and o1) of the step's 4 columns; z[T][p][ri] when all 16
+// entries vanish (36 of 1,024 tiles with this schedule). The kernel skips
+// them; mfma4_arrange_operators checks that the operator is zero there.
+struct ZeroTiles4 {
+    bool z[32][8][4];
+    static constexpr bool zero_entry(int p, int row, int col) {
+        const int d = col & 63;
+        const int dx[3] = {d & 3, (d >> 2) & 3, d >> 4};
+        for (int x = 0; x < 3; ++x)
+            if (((p >> x) & 1) == 0 && ((row >> x) & 1) == 1 && dx[x] == 0) return true;
+        return false;
+    }
+    constexpr ZeroTiles4() : z() {
+        constexpr MfmaSchedule S{};
+        for (int t = 0; t < 32; ++t)
+            for (int p = 0; p < 8; ++p)
+                for (int ri = 0; ri < 4; ++ri) {
+                    bool all = true;
+                    for (int i = 0; i < 4; ++i)
+                        for (int k = 0; k < 4; ++k) all = all && zero_entry(p, 4 * i + ri, S.col[t][k]);
+                    z[t][p][ri] = all;
+                }
+    }
+};
+
 // Corner values s = 4 .. 7 (the upper z plane) of a cell, input column of step T.
 template <int T>
 __device__ __forceinline__ void load_upper(const double* __restrict__ src, size_t plane, const Cell16& c,
@@ -136,6 +166,7 @@ struct Steps4Pair {
                                                double (*acca)[4], double (*accb)[4], double (*ra)[8],
                                                double (*rb)[4]) {
         constexpr MfmaSchedule S{};
+        constexpr ZeroTiles4 Z{};
         constexpr int dp = S.dpar[T];
         if constexpr (T + kAhead4 < 32) {
             load_step<T + kAhead4>(src, plane, ca, packed, ra[(T + kAhead4) % kRing4]);
@@ -162,6 +193,7 @@ struct Steps4Pair {
             }
 #pragma unroll
             for (int ri = 0; ri < 4; ++ri) {
+                if (Z.z[T][p][ri]) continue;  // resolved at compile time
                 const double2 av = a[p & 1][ri >> 1];
                 const double x = (ri & 1) ? av.y : av.x;
                 acca[p][ri] = __builtin_amdgcn_mfma_f64_4x4x4f64(x, Ta[p ^ dp], acca[p][ri], 0, 0, 0);
@@ -431,19 +463,25 @@ hipError_t launch_fused_mfma_slab(const double* src, double* dst, const double* 
     return hipGetLastError();
 }
 
-void mfma4_arrange_operators(const double* K, double* K4) {
+bool mfma4_arrange_operators(const double* K, double* K4) {
     // K: [8][16][128] canonical class operators. Tile ri = 2 rp + h of class p
     // at step t: A[i][k] = K[p][4 i + ri][col(t, k)], stored at
     // ((((t 8 + p) 2 + rp) 16 + 4 k + i) 2 + h: a lane reads its two tiles of
-    // a row-tile pair as one 16-byte value.
+    // a row-tile pair as one 16-byte value. Returns false if a tile that the
+    // kernels skip (ZeroTiles4) holds a nonzero entry.
     constexpr MfmaSchedule S{};
+    constexpr ZeroTiles4 Z{};
+    bool ok = true;
     for (int t = 0; t < 32; ++t)
         for (int p = 0; p < 8; ++p)
             for (int ri = 0; ri < 4; ++ri)
                 for (int k = 0; k < 4; ++k)
-                    for (int i = 0; i < 4; ++i)
-                        K4[((((size_t)t * 8 + p) * 2 + (ri >> 1)) * 16 + 4 * k + i) * 2 + (ri & 1)] =
-                            K[((size_t)p * 16 + 4 * i + ri) * 128 + S.col[t][k]];
+                    for (int i = 0; i < 4; ++i) {
+                        const double v = K[((size_t)p * 16 + 4 * i + ri) * 128 + S.col[t][k]];
+                        K4[((((size_t)t * 8 + p) * 2 + (ri >> 1)) * 16 + 4 * k + i) * 2 + (ri & 1)] = v;
+                        if (Z.z[t][p][ri] && v != 0.0) ok = false;
+                    }
+    return ok;
 }
 
 hipError_t launch_fused_mfma4_slab(const double* src, double* dst, const double* K4, int n, int k0, int k1,

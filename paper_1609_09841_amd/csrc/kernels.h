@@ -35,7 +35,8 @@ size_t mfma_operator_doubles();
 constexpr size_t kMfma4QueueWords = 8 * 64;
 hipError_t launch_fused_mfma4(const double* src, double* dst, const double* K4, int n, size_t pitch, int off, int grid,
                               uint32_t* queue, hipStream_t st);
-void mfma4_arrange_operators(const double* K, double* K4);
+// false if a tile the 4x4 kernels skip as structurally zero is not zero in K
+bool mfma4_arrange_operators(const double* K, double* K4);
 // Cell planes k0 .. k1-1 (no launch if empty) of a z-slab on the 4x4-tile
 // instruction, two z-adjacent batches per wave; K4 and queue as for
 // launch_fused_mfma4.

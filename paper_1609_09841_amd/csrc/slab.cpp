@@ -170,7 +170,8 @@ int hermite_slab_create(int n_cells, int nz, int m, double cfl, double c, const 
     e = hipMemcpy(s->K, Kperm.data(), Kperm.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(shipfail(s, e, "upload K"));
     std::vector<double> K4(hermite::mfma_operator_doubles());
-    hermite::mfma4_arrange_operators(K.data(), K4.data());
+    if (!hermite::mfma4_arrange_operators(K.data(), K4.data()))
+        return bail(sfail(s, HERMITE_EUNSUPPORTED, "class operator has a nonzero entry the kernel skips"));
     e = hipMalloc(&s->K4, K4.size() * sizeof(double));
     if (e != hipSuccess) return bail(shipfail(s, e, "hipMalloc(K4)"));
     e = hipMemcpy(s->K4, K4.data(), K4.size() * sizeof(double), hipMemcpyHostToDevice);
