@@ -114,7 +114,7 @@ constexpr int kRing4 = kAhead4 + 1;
 // no second-order term from the values, and the evolution lowers orders in
 // steps of two). Tile ri of class p at step T holds rows 4 i + ri (i = field
 // and o3, ri = o2 and o1) of the step's 4 columns; z[T][p][ri] when all 16
-// entries vanish (36 of 1,024 tiles with this schedule). The kernel skips
+// entries vanish (124 of 1,024 tiles with this schedule). The kernel skips
 // them; mfma4_arrange_operators checks that the operator is zero there.
 struct ZeroTiles4 {
     bool z[32][8][4];
